@@ -1,0 +1,219 @@
+"""Plain FP64 CPU oracle of the relativistic PIC step (arXiv 1906.06306).
+
+TEST INFRASTRUCTURE ONLY: only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  It shares no code
+with the HIP implementation in ``paper_1906_06306_amd``; both consume the
+seeded inputs of ``synth``.
+
+``pic_oracle.c`` holds the arithmetic (global periodic arrays, Table-1 order,
+double precision, no FMA contraction); this module is argument marshalling
+plus the tile-level integer rules in :mod:`oracle.tiles`.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pic_oracle.c")
+_LIB = os.path.join(_HERE, "_build", "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc -O2 -ffp-contract=off."""
+    os.makedirs(os.path.dirname(_LIB), exist_ok=True)
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+                               "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I = ctypes.c_int
+        I64 = ctypes.c_int64
+        Dbl = ctypes.c_double
+        sig = {
+            "orc_advance_b": (None, [I, P, Dbl, P, P]),
+            "orc_advance_e": (None, [I, P, Dbl, P, P]),
+            "orc_add_current": (None, [P, P, P]),
+            "orc_interp": (None, [I, P, P, P, I64, P, P, P]),
+            "orc_boris": (None, [I64, Dbl, Dbl, P, P, P]),
+            "orc_move": (None, [I, I64, Dbl, P, P, P]),
+            "orc_zigzag": (None, [I, P, Dbl, I64, P, P, P, P]),
+            "orc_wrap": (None, [I, P, I64, P]),
+            "orc_step": (I, [I, P, Dbl, I, P, P, P, P, P, P, P, P]),
+            "orc_rho": (None, [I, P, Dbl, I64, P, P]),
+            "orc_div_edge": (None, [P, P, P]),
+            "orc_div_face": (None, [P, P, P]),
+            "orc_field_energy": (Dbl, [P, P, P]),
+            "orc_kinetic_energy": (Dbl, [I64, Dbl, Dbl, P]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 or a.dtype == np.int32 or a.dtype == np.int64, a.dtype
+    assert a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dims(n) -> np.ndarray:
+    return np.ascontiguousarray(np.array(list(n) + [1] * (3 - len(n)), dtype=np.int32))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ------------------------------------------------------------------ fields
+
+def advance_b(D, n, h, E, B):
+    """B -= h curl+(E) (in place on B)."""
+    dims = _dims(n)
+    lib().orc_advance_b(D, _p(dims), float(h), _p(E), _p(B))
+
+
+def advance_e(D, n, h, B, E):
+    """E += h curl-(B) (in place on E)."""
+    dims = _dims(n)
+    lib().orc_advance_e(D, _p(dims), float(h), _p(B), _p(E))
+
+
+def add_current(n, J, E):
+    dims = _dims(n)
+    lib().orc_add_current(_p(dims), _p(J), _p(E))
+
+
+# --------------------------------------------------------------- particles
+
+def interp(D, n, E, B, x):
+    x = _f64(x)
+    np_ = x.shape[1]
+    Ep = np.zeros((3, np_))
+    Bp = np.zeros((3, np_))
+    dims = _dims(n)
+    lib().orc_interp(D, _p(dims), _p(E), _p(B), np_, _p(x), _p(Ep), _p(Bp))
+    return Ep, Bp
+
+
+def boris(c, s, Ep, Bp, u):
+    """u (3, np) updated in place."""
+    lib().orc_boris(u.shape[1], float(c), float(s), _p(_f64(Ep)), _p(_f64(Bp)), _p(u))
+
+
+def move(D, c, u, x):
+    """x (D, np) advanced in place; returns the (3, np) displacement."""
+    disp = np.zeros((3, u.shape[1]))
+    lib().orc_move(D, u.shape[1], float(c), _p(u), _p(x), _p(disp))
+    return disp
+
+
+def zigzag(D, n, q, x1, x2, disp, J):
+    dims = _dims(n)
+    lib().orc_zigzag(D, _p(dims), float(q), x1.shape[1], _p(_f64(x1)), _p(_f64(x2)),
+                     _p(_f64(disp)), _p(J))
+
+
+def wrap(D, n, x):
+    dims = _dims(n)
+    lib().orc_wrap(D, _p(dims), x.shape[1], _p(x))
+
+
+def rho(D, n, q, x, out=None):
+    dims = _dims(n)
+    N = int(np.prod(dims))
+    if out is None:
+        out = np.zeros(N)
+    lib().orc_rho(D, _p(dims), float(q), x.shape[1], _p(_f64(x)), _p(out))
+    return out
+
+
+def div_edge(n, F):
+    dims = _dims(n)
+    out = np.zeros(int(np.prod(dims)))
+    lib().orc_div_edge(_p(dims), _p(_f64(F)), _p(out))
+    return out
+
+
+def div_face(n, F):
+    dims = _dims(n)
+    out = np.zeros(int(np.prod(dims)))
+    lib().orc_div_face(_p(dims), _p(_f64(F)), _p(out))
+    return out
+
+
+def field_energy(n, E, B):
+    dims = _dims(n)
+    return lib().orc_field_energy(_p(dims), _p(_f64(E)), _p(_f64(B)))
+
+
+def kinetic_energy(mass, c, u):
+    return lib().orc_kinetic_energy(u.shape[1], float(mass), float(c), _p(_f64(u)))
+
+
+# -------------------------------------------------------------- full step
+
+class State:
+    """Mutable FP64 copy of a synth.Plasma for stepping with the oracle."""
+
+    def __init__(self, plasma):
+        self.D = plasma.D
+        self.n = tuple(plasma.n)
+        self.c = float(plasma.c)
+        self.E = _f64(plasma.E).copy()
+        self.B = _f64(plasma.B).copy()
+        self.J = np.zeros_like(self.E)
+        self.x = [_f64(s.x).copy() for s in plasma.species]
+        self.u = [_f64(s.u).copy() for s in plasma.species]
+        self.q = [float(s.q) for s in plasma.species]
+        self.s = [float(s.s) for s in plasma.species]
+        self.m = [float(s.m) for s in plasma.species]
+
+    def step(self, nsteps: int = 1):
+        ns = len(self.x)
+        dims = _dims(self.n)
+        n_per = np.array([x.shape[1] for x in self.x], dtype=np.int64)
+        xp = (ctypes.c_void_p * ns)(*[x.ctypes.data for x in self.x])
+        up = (ctypes.c_void_p * ns)(*[u.ctypes.data for u in self.u])
+        q = np.array(self.q, dtype=np.float64)
+        s = np.array(self.s, dtype=np.float64)
+        for _ in range(nsteps):
+            rc = lib().orc_step(self.D, _p(dims), self.c, ns, _p(n_per),
+                                ctypes.cast(xp, ctypes.c_void_p), ctypes.cast(up, ctypes.c_void_p),
+                                _p(q), _p(s), _p(self.E), _p(self.B), _p(self.J))
+            if rc != 0:
+                raise MemoryError("oracle step could not allocate scratch")
+
+    def rho(self):
+        out = np.zeros(int(np.prod(_dims(self.n))))
+        for x, q in zip(self.x, self.q):
+            rho(self.D, self.n, q, x, out)
+        return out
+
+    def gauss_residual(self):
+        return div_edge(self.n, self.E) - self.rho()
+
+    def div_b(self):
+        return div_face(self.n, self.B)
+
+    def energies(self):
+        uf = field_energy(self.n, self.E, self.B)
+        uk = sum(kinetic_energy(m, self.c, u) for m, u in zip(self.m, self.u))
+        return uf, uk

@@ -1,0 +1,408 @@
+/*
+ * Plain FP64 CPU oracle of the relativistic particle-in-cell step of
+ * Nattila, "Runko: Modern multiphysics toolbox for plasma simulations"
+ * (arXiv 1906.06306).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the tests, the smoke check and the CPU-baseline leg
+ * of the benchmark do.  It shares no code, header or constant with the HIP
+ * implementation.
+ *
+ * Everything is written on global (untiled) periodic arrays, in double
+ * precision, in the order the paper's time-advance loop (Table 1) lists the
+ * routines, without blocking, fusion or reordering.  Build with
+ * -O2 -ffp-contract=off so that no multiply-add is contracted.
+ *
+ * Lattice (Sect. 2.3.1, the Yee staggering of the main text): storage index
+ * (i,j,k) holds
+ *   Ex at (i+1/2, j, k)     Ey at (i, j+1/2, k)     Ez at (i, j, k+1/2)
+ *   Bx at (i, j+1/2, k+1/2) By at (i+1/2, j, k+1/2) Bz at (i+1/2, j+1/2, k)
+ * J is co-located with E, the charge density rho sits on nodes (i,j,k).
+ * Dimensions at or beyond D have extent 1; with periodic wrapping every
+ * difference along them vanishes, which is the lower-dimensional lattice.
+ * Field arrays are three planes of N = n0*n1*n2 values, x fastest.
+ * Particle positions are global, in cell units, D values per particle
+ * (plane per dimension); four-velocities u have 3 planes.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+static int64_t wrapi(int64_t i, int64_t n)
+{
+    int64_t r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+static int64_t cell(const int n[3], int64_t i, int64_t j, int64_t k)
+{
+    return wrapi(i, n[0]) + (int64_t)n[0] * (wrapi(j, n[1]) + (int64_t)n[1] * wrapi(k, n[2]));
+}
+
+static int64_t ncells(const int n[3]) { return (int64_t)n[0] * n[1] * n[2]; }
+
+/* ---------------------------------------------------------------------- */
+/* Field solver, Eqs. (fdE)/(fdB) with the forward/backward differences of
+ * App. B, on the main-text lattice.                                       */
+
+/* B <- B - h * curl(E), curl taken with forward differences so that each
+ * B component lands on its own staggered point.  One half-step of the
+ * split B advance of Table 1 uses h = c/2.                                */
+void orc_advance_b(int D, const int n[3], double h, const double *E, double *B)
+{
+    (void)D;
+    int64_t N = ncells(n);
+    const double *Ex = E, *Ey = E + N, *Ez = E + 2 * N;
+    double *Bx = B, *By = B + N, *Bz = B + 2 * N;
+    for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j)
+            for (int i = 0; i < n[0]; ++i) {
+                int64_t c = cell(n, i, j, k);
+                int64_t ip = cell(n, i + 1, j, k), jp = cell(n, i, j + 1, k), kp = cell(n, i, j, k + 1);
+                double cx = (Ez[jp] - Ez[c]) - (Ey[kp] - Ey[c]);
+                double cy = (Ex[kp] - Ex[c]) - (Ez[ip] - Ez[c]);
+                double cz = (Ey[ip] - Ey[c]) - (Ex[jp] - Ex[c]);
+                Bx[c] -= h * cx;
+                By[c] -= h * cy;
+                Bz[c] -= h * cz;
+            }
+}
+
+/* E <- E + h * curl(B), backward differences.  push_e of Table 1 uses h=c. */
+void orc_advance_e(int D, const int n[3], double h, const double *B, double *E)
+{
+    (void)D;
+    int64_t N = ncells(n);
+    const double *Bx = B, *By = B + N, *Bz = B + 2 * N;
+    double *Ex = E, *Ey = E + N, *Ez = E + 2 * N;
+    for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j)
+            for (int i = 0; i < n[0]; ++i) {
+                int64_t c = cell(n, i, j, k);
+                int64_t im = cell(n, i - 1, j, k), jm = cell(n, i, j - 1, k), km = cell(n, i, j, k - 1);
+                double cx = (Bz[c] - Bz[jm]) - (By[c] - By[km]);
+                double cy = (Bx[c] - Bx[km]) - (Bz[c] - Bz[im]);
+                double cz = (By[c] - By[im]) - (Bx[c] - Bx[jm]);
+                Ex[c] += h * cx;
+                Ey[c] += h * cy;
+                Ez[c] += h * cz;
+            }
+}
+
+/* add_cur of Table 1: E <- E - J (J already in field units, Eq. fdE). */
+void orc_add_current(const int n[3], const double *J, double *E)
+{
+    int64_t M = 3 * ncells(n);
+    for (int64_t m = 0; m < M; ++m) E[m] -= J[m];
+}
+
+/* ---------------------------------------------------------------------- */
+/* Particles.                                                              */
+
+/* staggering offset of field component comp (0..2 = E, 3..5 = B) along d */
+static double stagger(int comp, int d)
+{
+    static const double off[6][3] = {
+        {0.5, 0.0, 0.0}, {0.0, 0.5, 0.0}, {0.0, 0.0, 0.5},
+        {0.0, 0.5, 0.5}, {0.5, 0.0, 0.5}, {0.5, 0.5, 0.0},
+    };
+    return off[comp][d];
+}
+
+/* Linear ("volume averaging") interpolation, Sect. 2.3.2: every component
+ * is interpolated from its own staggered sub-lattice with first-order
+ * (cloud-in-cell) weights over the 2^D surrounding points.
+ * x: D planes of np global positions.  Out: 3 planes each of Ep, Bp.      */
+void orc_interp(int D, const int n[3], const double *E, const double *B,
+                int64_t np, const double *x, double *Ep, double *Bp)
+{
+    int64_t N = ncells(n);
+    for (int64_t p = 0; p < np; ++p) {
+        for (int comp = 0; comp < 6; ++comp) {
+            const double *F = comp < 3 ? E + comp * N : B + (comp - 3) * N;
+            int64_t base[3] = {0, 0, 0};
+            double w[3] = {0.0, 0.0, 0.0};
+            for (int d = 0; d < D; ++d) {
+                double xi = x[d * np + p] - stagger(comp, d);
+                double fl = floor(xi);
+                base[d] = (int64_t)fl;
+                w[d] = xi - fl;
+            }
+            double acc = 0.0;
+            int ncorner = 1 << D;
+            for (int cn = 0; cn < ncorner; ++cn) {
+                int64_t idx[3] = {base[0], base[1], base[2]};
+                double wt = 1.0;
+                for (int d = 0; d < D; ++d) {
+                    int bit = (cn >> d) & 1;
+                    idx[d] += bit;
+                    wt *= bit ? w[d] : 1.0 - w[d];
+                }
+                acc += wt * F[cell(n, idx[0], idx[1], idx[2])];
+            }
+            if (comp < 3) Ep[comp * np + p] = acc;
+            else Bp[(comp - 3) * np + p] = acc;
+        }
+    }
+}
+
+/* Relativistic Boris velocity update, App. C.  Velocities are carried in
+ * units of the Courant number c inside the update (u' = c u).
+ * s = q/(m m_pm), the species charge-to-mass factor of App. C.
+ * u: 3 planes, updated in place from u^{n-1/2} to u^{n+1/2}.              */
+void orc_boris(int64_t np, double c, double s, const double *Ep, const double *Bp, double *u)
+{
+    for (int64_t p = 0; p < np; ++p) {
+        double ex = 0.5 * s * Ep[p], ey = 0.5 * s * Ep[np + p], ez = 0.5 * s * Ep[2 * np + p];
+        /* first half of the electric kick */
+        double u1x = c * u[p] + ex, u1y = c * u[np + p] + ey, u1z = c * u[2 * np + p] + ez;
+        double g1 = sqrt(1.0 + (u1x * u1x + u1y * u1y + u1z * u1z) / (c * c));
+        /* rotation vector t = s B / (2 c gamma_1) and f = 2/(1+|t|^2) */
+        double tx = s * Bp[p] / (2.0 * c * g1);
+        double ty = s * Bp[np + p] / (2.0 * c * g1);
+        double tz = s * Bp[2 * np + p] / (2.0 * c * g1);
+        double f = 2.0 / (1.0 + (tx * tx + ty * ty + tz * tz));
+        /* u2' = f (u1' + u1' x t) */
+        double u2x = f * (u1x + (u1y * tz - u1z * ty));
+        double u2y = f * (u1y + (u1z * tx - u1x * tz));
+        double u2z = f * (u1z + (u1x * ty - u1y * tx));
+        /* u3' = u1' + u2' x t + second half of the electric kick */
+        double u3x = u1x + (u2y * tz - u2z * ty) + ex;
+        double u3y = u1y + (u2z * tx - u2x * tz) + ey;
+        double u3z = u1z + (u2x * ty - u2y * tx) + ez;
+        u[p] = u3x / c;
+        u[np + p] = u3y / c;
+        u[2 * np + p] = u3z / c;
+    }
+}
+
+/* Position advance, Eq. (fdX): dx = c u / gamma with gamma of u^{n+1/2}.
+ * All three displacement components are returned in disp (3 planes); the
+ * D grid coordinates of x are advanced in place (no wrapping here).       */
+void orc_move(int D, int64_t np, double c, const double *u, double *x, double *disp)
+{
+    for (int64_t p = 0; p < np; ++p) {
+        double ux = u[p], uy = u[np + p], uz = u[2 * np + p];
+        double g = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
+        double dv[3] = {c * ux / g, c * uy / g, c * uz / g};
+        for (int m = 0; m < 3; ++m) disp[m * np + p] = dv[m];
+        for (int d = 0; d < D; ++d) x[d * np + p] += dv[d];
+    }
+}
+
+/* Deposit one zigzag segment: flux F (3 comps), weight W, displacement dv
+ * and cell i along the grid dimensions.  A segment is a straight move inside
+ * one cell, so its current is the path average of the first-order particle
+ * shape.  Component m goes to J_m at the cell index along m and, along every
+ * other grid dimension d, to the two points i_d, i_d+1 with the linear
+ * weights 1-W_d and W_d evaluated at the segment midpoint.  When two such
+ * transverse dimensions a, b exist, the path average of the product of the
+ * two linear factors adds sigma_a sigma_b dv_a dv_b / 12 (sigma = -1 at the
+ * lower point, +1 at the upper point); without it the deposit would not
+ * satisfy the discrete continuity equation in 3D.                        */
+static void deposit_segment(int D, const int n[3], double *J, const double F[3],
+                            const double W[3], const double dv[3], const int64_t i[3])
+{
+    int64_t N = ncells(n);
+    for (int m = 0; m < 3; ++m) {
+        int ntrans = 0;
+        for (int d = 0; d < D; ++d) ntrans += (d != m);
+        int ncorner = 1 << D;
+        for (int cn = 0; cn < ncorner; ++cn) {
+            /* corners along dimension m itself do not exist */
+            if (m < D && ((cn >> m) & 1)) continue;
+            int64_t idx[3] = {i[0], i[1], i[2]};
+            double wt = 1.0, cross = 1.0;
+            for (int d = 0; d < D; ++d) {
+                if (d == m) continue;
+                int bit = (cn >> d) & 1;
+                idx[d] += bit;
+                wt *= bit ? W[d] : 1.0 - W[d];
+                cross *= bit ? dv[d] : -dv[d];
+            }
+            if (ntrans == 2) wt += cross / 12.0;
+            J[m * N + cell(n, idx[0], idx[1], idx[2])] += F[m] * wt;
+        }
+    }
+}
+
+/* Charge-conserving ZigZag deposit, App. D (after Umeda et al. 2003), of
+ * every particle moving from x1 to x2 (D planes each, unwrapped) with
+ * charge q.  disp holds the three displacement components; the ones along
+ * non-grid dimensions are split evenly over the two segments (relay point
+ * at the midpoint).  J is accumulated (not cleared) with periodic wrap.   */
+void orc_zigzag(int D, const int n[3], double q, int64_t np, const double *x1,
+                const double *x2, const double *disp, double *J)
+{
+    for (int64_t p = 0; p < np; ++p) {
+        double F1[3], F2[3], W1[3] = {0, 0, 0}, W2[3] = {0, 0, 0};
+        double d1[3] = {0, 0, 0}, d2[3] = {0, 0, 0};
+        int64_t i1[3] = {0, 0, 0}, i2[3] = {0, 0, 0};
+        for (int d = 0; d < 3; ++d) {
+            if (d < D) {
+                double a = x1[d * np + p], b = x2[d * np + p];
+                double fa = floor(a), fb = floor(b);
+                double lo = fa < fb ? fa : fb, hi = fa > fb ? fa : fb;
+                double mid = 0.5 * (a + b);
+                double inner = hi > mid ? hi : mid;      /* max{max{i1,i2}, mid} */
+                double xr = (lo + 1.0) < inner ? (lo + 1.0) : inner; /* min{min{i1,i2}+1, .} */
+                F1[d] = q * (xr - a);
+                F2[d] = q * (b - xr);
+                W1[d] = 0.5 * (a + xr) - fa;
+                W2[d] = 0.5 * (b + xr) - fb;
+                d1[d] = xr - a;
+                d2[d] = b - xr;
+                i1[d] = (int64_t)fa;
+                i2[d] = (int64_t)fb;
+            } else {
+                double h = 0.5 * disp[d * np + p];
+                F1[d] = q * h;
+                F2[d] = q * h;
+            }
+        }
+        deposit_segment(D, n, J, F1, W1, d1, i1);
+        deposit_segment(D, n, J, F2, W2, d2, i2);
+    }
+}
+
+/* Periodic wrap into [0, n): a result that rounds up to n becomes 0. */
+void orc_wrap(int D, const int n[3], int64_t np, double *x)
+{
+    for (int d = 0; d < D; ++d) {
+        double L = (double)n[d];
+        for (int64_t p = 0; p < np; ++p) {
+            double v = x[d * np + p];
+            if (v < 0.0) v += L;
+            else if (v >= L) v -= L;
+            if (v >= L) v = 0.0;
+            x[d * np + p] = v;
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* One full time step, routines in the order of Table 1:
+ *   push_half_b1; interp_em + push (every species); push_half_b2; push_e;
+ *   comp_curr (every species, J cleared first); the particle
+ *   communication rows, which on one periodic domain reduce to wrapping the
+ *   positions; add_cur.
+ * Species s has n_per[s] particles, positions x[s] (D planes, global) and
+ * four-velocities u[s] (3 planes); q[s] is its charge, sgn[s] its App. C
+ * factor s.  J is overwritten with this step's current.  Returns 0, or -1
+ * if scratch memory could not be allocated.                               */
+int orc_step(int D, const int n[3], double c, int nspecies, const int64_t *n_per,
+             double **x, double **u, const double *q, const double *sgn,
+             double *E, double *B, double *J)
+{
+    int64_t N = ncells(n);
+    double **xold = calloc((size_t)nspecies, sizeof(double *));
+    double **disp = calloc((size_t)nspecies, sizeof(double *));
+    int64_t npmax = 1;
+    for (int s = 0; s < nspecies; ++s) npmax = n_per[s] > npmax ? n_per[s] : npmax;
+    double *fp = malloc(sizeof(double) * 6 * (size_t)npmax);
+    int ok = xold && disp && fp;
+    for (int s = 0; ok && s < nspecies; ++s) {
+        xold[s] = malloc(sizeof(double) * (size_t)(D * n_per[s] + 1));
+        disp[s] = malloc(sizeof(double) * (size_t)(3 * n_per[s] + 1));
+        ok = xold[s] && disp[s];
+    }
+    if (ok) {
+        orc_advance_b(D, n, 0.5 * c, E, B);                       /* push_half_b1 */
+        for (int s = 0; s < nspecies; ++s) {                       /* interp_em, push */
+            int64_t np = n_per[s];
+            memcpy(xold[s], x[s], sizeof(double) * (size_t)(D * np));
+            orc_interp(D, n, E, B, np, x[s], fp, fp + 3 * np);
+            orc_boris(np, c, sgn[s], fp, fp + 3 * np, u[s]);
+            orc_move(D, np, c, u[s], x[s], disp[s]);
+        }
+        orc_advance_b(D, n, 0.5 * c, E, B);                       /* push_half_b2 */
+        orc_advance_e(D, n, c, B, E);                             /* push_e */
+        memset(J, 0, sizeof(double) * 3 * (size_t)N);             /* comp_curr */
+        for (int s = 0; s < nspecies; ++s)
+            orc_zigzag(D, n, q[s], n_per[s], xold[s], x[s], disp[s], J);
+        for (int s = 0; s < nspecies; ++s) orc_wrap(D, n, n_per[s], x[s]);
+        orc_add_current(n, J, E);                                 /* add_cur */
+    }
+    for (int s = 0; xold && disp && s < nspecies; ++s) {
+        free(xold[s]);
+        free(disp[s]);
+    }
+    free(xold);
+    free(disp);
+    free(fp);
+    return ok ? 0 : -1;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Diagnostics (the paper prints no formula; these follow from App. B).   */
+
+/* Charge density on nodes: cloud-in-cell weights of each particle times q.
+ * rho is accumulated (not cleared). */
+void orc_rho(int D, const int n[3], double q, int64_t np, const double *x, double *rho)
+{
+    for (int64_t p = 0; p < np; ++p) {
+        int64_t base[3] = {0, 0, 0};
+        double w[3] = {0, 0, 0};
+        for (int d = 0; d < D; ++d) {
+            double fl = floor(x[d * np + p]);
+            base[d] = (int64_t)fl;
+            w[d] = x[d * np + p] - fl;
+        }
+        for (int cn = 0; cn < (1 << D); ++cn) {
+            int64_t idx[3] = {base[0], base[1], base[2]};
+            double wt = 1.0;
+            for (int d = 0; d < D; ++d) {
+                int bit = (cn >> d) & 1;
+                idx[d] += bit;
+                wt *= bit ? w[d] : 1.0 - w[d];
+            }
+            rho[cell(n, idx[0], idx[1], idx[2])] += q * wt;
+        }
+    }
+}
+
+/* Backward-difference divergence of an E-like (edge) field, on nodes. */
+void orc_div_edge(const int n[3], const double *F, double *out)
+{
+    int64_t N = ncells(n);
+    for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j)
+            for (int i = 0; i < n[0]; ++i) {
+                int64_t c = cell(n, i, j, k);
+                out[c] = (F[c] - F[cell(n, i - 1, j, k)]) + (F[N + c] - F[N + cell(n, i, j - 1, k)]) +
+                         (F[2 * N + c] - F[2 * N + cell(n, i, j, k - 1)]);
+            }
+}
+
+/* Forward-difference divergence of a B-like (face) field, on cell centres. */
+void orc_div_face(const int n[3], const double *F, double *out)
+{
+    int64_t N = ncells(n);
+    for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j)
+            for (int i = 0; i < n[0]; ++i) {
+                int64_t c = cell(n, i, j, k);
+                out[c] = (F[cell(n, i + 1, j, k)] - F[c]) + (F[N + cell(n, i, j + 1, k)] - F[N + c]) +
+                         (F[2 * N + cell(n, i, j, k + 1)] - F[2 * N + c]);
+            }
+}
+
+/* Field energy 1/2 sum(E^2 + B^2) and kinetic energy sum m c^2 (gamma-1). */
+double orc_field_energy(const int n[3], const double *E, const double *B)
+{
+    int64_t M = 3 * ncells(n);
+    double s = 0.0;
+    for (int64_t m = 0; m < M; ++m) s += E[m] * E[m] + B[m] * B[m];
+    return 0.5 * s;
+}
+
+double orc_kinetic_energy(int64_t np, double mass, double c, const double *u)
+{
+    double s = 0.0;
+    for (int64_t p = 0; p < np; ++p) {
+        double g = sqrt(1.0 + u[p] * u[p] + u[np + p] * u[np + p] + u[2 * np + p] * u[2 * np + p]);
+        s += g - 1.0;
+    }
+    return mass * c * c * s;
+}
