@@ -1,0 +1,191 @@
+#!/usr/bin/env python3
+"""Throughput of the relativistic PIC step on one MI355X.
+
+Workload: 2D3V decaying relativistic turbulence, 1024 x 1024 periodic cells,
+32 x 32 tiles, 16 particles per cell per species (pair plasma, 33.5 M
+particles), Maxwell-Juttner theta = 0.3, guide field from sigma = 10,
+64 random-phase forcing modes at dB = B0, skin depth 3 cells, Courant 0.45.
+One step = the whole hot path: half B update, fused interpolation + Boris
+push + ZigZag deposit + tile pack, half B update, current halo fold,
+E update with current, tile migration.
+
+Prints ONE JSON line: particle-steps/s of the FP32 path (value), the FP64
+path beside it, the roofline of the dominant kernel (the fused push) from
+HIP events on its stream, and the FP64 CPU oracle timed on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "particle-steps/sec (push+deposit+FDTD) FP32 vs FP64 at 1 GPU; % HBM roofline"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=1024, help="cells per side")
+    ap.add_argument("--ppc", type=int, default=16, help="particles per cell per species")
+    ap.add_argument("--tile", type=int, default=32)
+    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="only run this many fused steps (for rocprofv3), no JSON")
+    return ap.parse_args()
+
+
+def algorithmic_bytes(D, w, n_particles, n_cells):
+    """Bytes the step must move: every particle's D positions and 3
+    momenta read and written once; E and B (6 words) read and written once
+    and J (3 words) written and read once per cell."""
+    return n_particles * 2 * (D + 3) * w + n_cells * 18 * w
+
+
+def push_bytes(D, w, n_particles, n_cells):
+    """Bytes the fused push kernel must move per launch: particles read and
+    written once, E and B read once, the current written once."""
+    return n_particles * 2 * (D + 3) * w + n_cells * 9 * w
+
+
+def run_gpu(plasma, args, precision, steps, warmup, profile_only=False):
+    import torch
+    from paper_1906_06306_amd import _lib as L
+    from paper_1906_06306_amd.sim import PicSim
+
+    sim = PicSim(plasma, tile=(args.tile, args.tile), precision=precision, block=args.block)
+    stream = torch.cuda.current_stream()
+    lib = L.lib()
+    ctx = sim.ctx
+
+    def step(ev=None):
+        L.check(lib.pic_fdtd_step(ctx, L.PIC_HALF_B))
+        if ev is not None:
+            ev[0].record(stream)
+        L.check(lib.pic_push_interp(ctx, L.PIC_FUSED))
+        if ev is not None:
+            ev[1].record(stream)
+        L.check(lib.pic_fdtd_step(ctx, L.PIC_HALF_B))
+        L.check(lib.pic_deposit_current(ctx, L.PIC_FUSED))
+        L.check(lib.pic_fdtd_step(ctx, L.PIC_CURL_E_ADD_J))
+        L.check(lib.pic_sort_migrate(ctx, 0))
+
+    if profile_only:
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        code = sim.error()
+        sim.close()
+        return code
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    push_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    diag = sim.diagnostics()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return dict(seconds=dt, push_ms=push_ms, diag=diag)
+
+
+def cpu_oracle_rate(plasma):
+    """The FP64 oracle, as it stands, on one full step of the same workload."""
+    import oracle
+    st = oracle.State(plasma)
+    t0 = time.perf_counter()
+    st.step(1)
+    dt = time.perf_counter() - t0
+    return plasma.nparticles / dt, dt
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU tile decomposition is a design, not a build, here).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import synth
+
+    assert torch.cuda.is_available(), "no GPU"
+    t0 = time.perf_counter()
+    plasma = synth.turbulence(n=args.n, ppc=args.ppc)
+    log(f"generated {plasma.nparticles} particles on {args.n}^2 cells in {time.perf_counter() - t0:.1f}s")
+    n_p, n_c, D = plasma.nparticles, plasma.ncells, plasma.D
+    if args.profile_steps:
+        code = run_gpu(plasma, args, "fp32", args.profile_steps, 0, profile_only=True)
+        log(f"profile run done, device status {code}")
+        return
+    log("fp32 run")
+    r32 = run_gpu(plasma, args, "fp32", args.steps, args.warmup)
+    r64 = None
+    if not args.no_fp64:
+        log("fp64 run")
+        r64 = run_gpu(plasma, args, "fp64", args.steps, args.warmup)
+    cpu = None
+    if not args.no_cpu:
+        log("cpu oracle: one full step")
+        rate, sec = cpu_oracle_rate(plasma)
+        cpu = {"value": rate, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+               "sample": f"1 full step of the same {args.n}^2 workload ({n_p} particles), "
+                         f"single-threaded FP64 C oracle, {sec:.1f} s"}
+    value = n_p * args.steps / r32["seconds"]
+    pb = push_bytes(D, 4, n_p, n_c)
+    achieved = pb / (r32["push_ms"] * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["seconds"] / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"2D3V decaying turbulence {args.n}x{args.n} periodic, "
+                               f"{args.tile}x{args.tile} tiles, {args.ppc} ppc/species pair plasma, "
+                               "theta=0.3, sigma=10, dB/B0=1 (64 modes), c/w_p=3 cells, Courant 0.45",
+                   "particles": n_p, "cells": n_c, "block": args.block},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_push<float,2,fused>", "push_ms": r32["push_ms"],
+                     "algorithmic_bytes_per_launch": pb},
+        "step_roofline_frac": algorithmic_bytes(D, 4, n_p, n_c) * value / n_p / 1e9 / HBM_PEAK_GBS,
+        "diagnostics_fp32": {k: r32["diag"][k] for k in ("gauss_max", "divb_max", "field_energy",
+                                                         "kinetic_energy", "particles", "status")},
+        "cpu_baseline": cpu,
+    }
+    if r64 is not None:
+        v64 = n_p * args.steps / r64["seconds"]
+        out["fp64"] = {"value": v64, "ms_per_step": r64["seconds"] / args.steps * 1e3,
+                       "push_ms": r64["push_ms"], "speedup_fp32_over_fp64": value / v64,
+                       "gauss_max": r64["diag"]["gauss_max"]}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,232 @@
+/*
+ * libpic - MI355X (gfx950) implementation of the relativistic
+ * particle-in-cell step of Nattila, "Runko: Modern multiphysics toolbox for
+ * plasma simulations" (arXiv 1906.06306).
+ *
+ * One time step follows the paper's time-advance loop (Table 1):
+ *   pic_fdtd_step(PIC_HALF_B)          push_half_b1            Eq. (fdB)
+ *   pic_push_interp(...)               interp_em + push        Sect. 2.3.2,
+ *                                                              App. C, Eq. (fdX)
+ *   pic_fdtd_step(PIC_HALF_B)          push_half_b2            Eq. (fdB)
+ *   pic_deposit_current(...)           comp_curr, clear_vir_cur,
+ *                                      cur_exchange            App. D
+ *   pic_fdtd_step(PIC_CURL_E_ADD_J)    push_e + add_cur        Eq. (fdE)
+ *   pic_sort_migrate(...)              particle communication rows
+ * pic_step() enqueues exactly that sequence.
+ *
+ * Units (App. A): dx = dt = 1, Courant number c = cfl; E, B, J in code
+ * units; four-velocities u in units of the speed of light.
+ *
+ * Lattice (Sect. 2.3.1): each box stores, per component, one plane of
+ * n0*n1*n2 values, x fastest; storage index (i,j,k) holds
+ *   Ex (i+1/2,j,k)  Ey (i,j+1/2,k)  Ez (i,j,k+1/2)
+ *   Bx (i,j+1/2,k+1/2)  By (i+1/2,j,k+1/2)  Bz (i+1/2,j+1/2,k)
+ * and J is co-located with E.  Dimensions at or beyond `dim` have extent 1.
+ *
+ * Tiles (Sect. 3.1): every box is cut into tiles of tile[0] x tile[1] x
+ * tile[2] cells (even edges dividing the box).  Particles are stored per
+ * (tile, species) segment, structure of arrays, positions relative to the
+ * tile centre (x_loc in [-T/2, T/2) per grid dimension) in the chosen
+ * precision; the cell of a particle is floor(x_loc) + T/2.  Boxes are
+ * periodic and independent (a batch of boxes is stepped together).
+ *
+ * Memory: the caller allocates ONE device workspace of
+ * pic_layout.total_bytes (256-byte aligned) and owns it; the library never
+ * allocates or frees device memory.  Every region (fields, particles, tile
+ * tables, staging) is at the offsets pic_query() reports.  The library owns
+ * only the host-side context.
+ *
+ * Streams: a context is bound to one HIP stream; every call except
+ * pic_query, pic_error, pic_diagnostics and pic_destroy only enqueues work.
+ *
+ * Errors: functions return a pic_status.  Argument errors are returned at
+ * once (PIC_E_ARG, PIC_E_STATE); HIP runtime failures return PIC_E_HIP with
+ * text in pic_last_error().  Conditions found on the device (a full tile
+ * segment or outbox, a non-finite momentum, a displacement of a cell or
+ * more, a particle outside its tile) are latched as bits in a device word
+ * and returned by the next synchronising call (pic_error, pic_diagnostics).
+ * Particles are never dropped silently: an overflow sets PIC_E_CAPACITY and
+ * the state must be discarded.
+ */
+#ifndef PIC_H_
+#define PIC_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pic_status;
+
+/* synchronous status codes */
+#define PIC_OK 0
+#define PIC_E_ARG 1      /* invalid configuration or argument             */
+#define PIC_E_HIP 2      /* HIP runtime error, see pic_last_error()         */
+#define PIC_E_STATE 3    /* call out of order (e.g. deposit before push)    */
+/* device-latched bits (returned OR-ed, shifted left by 8) */
+#define PIC_E_CAPACITY (1 << 8)     /* tile segment or outbox overflow     */
+#define PIC_E_CFL (1 << 9)          /* |dx| >= 1 cell in one step          */
+#define PIC_E_NONFINITE (1 << 10)   /* NaN/Inf momentum or position        */
+#define PIC_E_OUT_OF_TILE (1 << 11) /* stored position outside its tile    */
+
+#define PIC_FP32 0
+#define PIC_FP64 1
+
+#define PIC_MAX_SPECIES 4
+
+/* pic_fdtd_step phases (Table 1 rows) */
+#define PIC_HALF_B 0        /* B -= (c/2) curl+ E        push_half_b1/b2  */
+#define PIC_CURL_E 1        /* E += c curl- B            push_e           */
+#define PIC_ADD_J 2         /* E -= J                    add_cur          */
+#define PIC_CURL_E_ADD_J 3  /* both, one pass (they commute)              */
+
+/* flags of pic_push_interp / pic_deposit_current / pic_sort_migrate */
+#define PIC_FUSED 1u        /* push also deposits J and moves leavers out  */
+#define PIC_SORT_CELLS 2u   /* stable sort by cell inside every tile        */
+
+typedef struct {
+    int32_t dim;          /* spatial dimensions D in {1,2,3}                 */
+    int32_t precision;    /* PIC_FP32 or PIC_FP64                           */
+    int32_t n_species;    /* 1..PIC_MAX_SPECIES                              */
+    int32_t n_boxes;      /* independent periodic boxes, >= 1                */
+    int32_t tile[3];      /* tile edge per dimension: even, >= 2, divides
+                             every box; 1 for dimensions >= dim             */
+    int32_t block;        /* threads per work-group of particle kernels
+                             (64..1024, multiple of 64); 0 = default 256    */
+    double cfl;           /* Courant number c, 0 < c <= 1/sqrt(D)           */
+    const int32_t *box_cells;   /* host [n_boxes][3] cells per dimension     */
+    const double *charge;       /* host [n_boxes][n_species] q (signed)      */
+    const double *qm;           /* host [n_boxes][n_species] App. C factor
+                                   s = q/(m m_pm) = sign(q)/m_pm             */
+    const double *mass;         /* host [n_boxes][n_species] macro-particle
+                                   mass (kinetic-energy diagnostic only)      */
+    const int64_t *tile_capacity; /* host [tiles][n_species] particles a
+                                   segment can hold, or NULL: see capacity   */
+    double capacity_factor;     /* if tile_capacity == NULL: segment capacity
+                                   = ceil(factor * count/tiles_in_box) + 64,
+                                   rounded up to 64 (default 1.25 if <= 0)    */
+    int32_t outbox_capacity;    /* leavers per (tile, species) per step; 0 =
+                                   default (a quarter of the segment, >= 256) */
+    int32_t reserved;
+} pic_config;
+
+/* Byte offsets of the regions inside the caller's workspace.  Fields:
+ * [3][cells_total] each, boxes concatenated (box b starts at cell offset
+ * box_cell_offset[b]).  Particles: [dim][capacity_total] positions and
+ * [3][capacity_total] four-velocities; segment (tile t, species s) starts at
+ * element seg_offset[t*n_species+s] (int64, device).  Counts: int32
+ * seg_count[t*n_species+s] (device).  elem = 4 (FP32) or 8 (FP64) bytes. */
+typedef struct {
+    uint64_t total_bytes;
+    uint64_t off_E, off_B, off_J;           /* elem [3][cells_total]          */
+    uint64_t off_pos, off_u;                /* elem [D|3][capacity_total]     */
+    uint64_t off_xold;                      /* elem [D][capacity_total]       */
+    uint64_t off_seg_offset;                /* int64 [tiles][species]          */
+    uint64_t off_seg_capacity;              /* int32 [tiles][species]          */
+    uint64_t off_seg_count;                 /* int32 [tiles][species]          */
+    uint64_t off_error;                     /* int32 latched device error bits */
+    uint64_t off_flags;                     /* int64 near-face counter          */
+    int64_t cells_total;
+    int64_t tiles_total;
+    int64_t capacity_total;
+    int64_t outbox_capacity;
+    int32_t elem_bytes;
+    int32_t reserved;
+} pic_layout;
+
+/* Initial state of box b, species s (index b*n_species+s), device
+ * pointers, FP64, global coordinates of that box in cells, [0, n_d):
+ * pos: [dim][count] planes, u: [3][count].  E, B: per box [3][cells]. */
+typedef struct {
+    const int64_t *count;          /* host [n_boxes][n_species]              */
+    const double *const *pos;      /* host array of device pointers          */
+    const double *const *u;        /* host array of device pointers          */
+    const double *const *E;        /* host array [n_boxes] of device ptrs    */
+    const double *const *B;        /* host array [n_boxes] of device ptrs    */
+} pic_init_data;
+
+/* FP64 diagnostics of the current state (Eqs. fdE/fdB, App. B). */
+typedef struct {
+    double field_energy;     /* 1/2 sum(E^2 + B^2) over all boxes           */
+    double kinetic_energy;   /* sum m c^2 (gamma - 1) over all particles     */
+    double gauss_max;        /* max |div- E - rho| on nodes                  */
+    double divb_max;         /* max |div+ B| on cell centres                 */
+    double charge_total;     /* sum rho                                      */
+    int64_t particles;       /* particles stored                            */
+    int64_t near_face;       /* particles flagged within 1 ulp of a cell face
+                                by the last init or sort                    */
+    int32_t error_bits;      /* latched device errors (then cleared)         */
+    int32_t reserved;
+} pic_diag;
+
+typedef struct pic_ctx pic_ctx;
+
+/* Workspace layout for a configuration and initial particle counts
+ * (host [n_boxes][n_species]).  Pure host computation.  PIC_E_ARG on an
+ * invalid configuration (tile not dividing a box, odd tile edge, cfl out
+ * of range, unsupported dim/precision/species count). */
+pic_status pic_query(const pic_config *cfg, const int64_t *counts, pic_layout *out);
+
+/* Bind a context to a workspace and stream, convert the initial FP64 state:
+ * bin particles by tile (stable: input order kept inside a tile), convert
+ * positions to tile-centre-relative coordinates in the working precision
+ * (a value that rounds onto the upper tile face moves to the next tile at
+ * -T/2), count particles within 1 ulp of a cell face, convert E and B, and
+ * zero J.  The workspace must be at least pic_query's total_bytes. */
+pic_status pic_init_tiles(const pic_config *cfg, const int64_t *counts, void *workspace,
+                          uint64_t workspace_bytes, const pic_init_data *init, void *hip_stream,
+                          pic_ctx **out);
+
+/* Field update on every box (Eqs. fdE/fdB with the forward and backward
+ * differences of App. B; periodic).  phase: PIC_HALF_B, PIC_CURL_E,
+ * PIC_ADD_J or PIC_CURL_E_ADD_J. */
+pic_status pic_fdtd_step(pic_ctx *ctx, int32_t phase);
+
+/* interp_em + push for every particle: linear interpolation of each E and B
+ * component from its own staggered lattice (Sect. 2.3.2), relativistic
+ * Boris update of u (App. C), position advance x += c u/gamma (Eq. fdX).
+ * Without PIC_FUSED the new positions are stored in place unrebased and
+ * the old ones in the xold region, for pic_deposit_current and
+ * pic_sort_migrate.  With PIC_FUSED the same work-group also deposits the
+ * ZigZag current of every particle into its tile's current block (App. D)
+ * and compacts the particles that stay, moving leavers to the tile outbox
+ * (the "tag outflowing / pack" rows of Table 1). */
+pic_status pic_push_interp(pic_ctx *ctx, uint32_t flags);
+
+/* comp_curr + clear_vir_cur + cur_exchange: after an unfused push, ZigZag
+ * deposit from (xold, x) into per-tile current blocks; in both modes, sum
+ * the blocks (tile plus halo) into J on the lattice. */
+pic_status pic_deposit_current(pic_ctx *ctx, uint32_t flags);
+
+/* Particle communication rows of Table 1: after an unfused push, move the
+ * particles that left each tile out (stable compaction); then every tile
+ * appends the arrivals from its neighbours (directions in increasing code
+ * sum (delta_d+1) 3^d, each in the sender's order) with positions rebased
+ * by -delta T (exact).  PIC_SORT_CELLS then sorts every tile segment
+ * stably by cell index (x fastest) and recounts near-face particles. */
+pic_status pic_sort_migrate(pic_ctx *ctx, uint32_t flags);
+
+/* One full time step in Table-1 order (see the top of this header);
+ * flags as for pic_push_interp, plus PIC_SORT_CELLS. */
+pic_status pic_step(pic_ctx *ctx, uint32_t flags);
+
+/* Synchronise the stream and return (then clear) the latched device error
+ * bits, or PIC_E_HIP. */
+pic_status pic_error(pic_ctx *ctx);
+
+/* FP64 diagnostics of the current state.  Synchronises the stream.  Its
+ * return value includes the latched device error bits (then cleared). */
+pic_status pic_diagnostics(pic_ctx *ctx, pic_diag *out);
+
+/* Release the host context (the workspace stays the caller's). */
+pic_status pic_destroy(pic_ctx *ctx);
+
+/* Text of the last error on this thread ("" if none). */
+const char *pic_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIC_H_ */

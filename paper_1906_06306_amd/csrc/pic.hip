@@ -1,0 +1,691 @@
+// libpic: C ABI of the MI355X relativistic PIC step (see include/pic.h).
+//
+// Host side: configuration checks, workspace layout, tile tables and kernel
+// launches on the context's stream.  All device memory belongs to the
+// caller's workspace; nothing here allocates device memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pic.h"
+#include "pic_aux_kernels.hpp"
+
+using pic::Params;
+using pic::TileDesc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+pic_status fail(pic_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_OK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) return fail(PIC_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+// Internal layout: the public offsets plus the staging regions.
+struct Layout {
+    pic_layout pub;
+    uint64_t off_tmp, off_jblk, off_rblk, off_part, off_ob_pos, off_ob_u, off_ob_dir, off_ob_cnt;
+    uint64_t off_tiles, off_charge, off_qm, off_mass, off_order, off_queue;
+    uint64_t off_key, off_xl, off_hist;
+    int64_t jblk_cells, rblk_cells, max_count, max_ntb, nchunks_max;
+    std::vector<TileDesc> tiles;
+    std::vector<int64_t> seg_off;
+    std::vector<int32_t> seg_cap;
+    std::vector<int64_t> box_cell0, box_tile0;
+    std::vector<int32_t> order;
+};
+
+int dims_of(const pic_config *c, int b, int d) { return d < c->dim ? c->box_cells[3 * b + d] : 1; }
+
+pic_status check_config(const pic_config *c)
+{
+    if (!c) return fail(PIC_E_ARG, "null config");
+    if (c->dim < 1 || c->dim > 3) return fail(PIC_E_ARG, "dim must be 1, 2 or 3 (got %d)", c->dim);
+    if (c->precision != PIC_FP32 && c->precision != PIC_FP64) return fail(PIC_E_ARG, "precision must be PIC_FP32 or PIC_FP64");
+    if (c->n_species < 1 || c->n_species > PIC_MAX_SPECIES) return fail(PIC_E_ARG, "n_species must be 1..%d", PIC_MAX_SPECIES);
+    if (c->n_boxes < 1) return fail(PIC_E_ARG, "n_boxes must be >= 1");
+    if (!c->box_cells || !c->charge || !c->qm || !c->mass) return fail(PIC_E_ARG, "box_cells, charge, qm and mass are required");
+    if (!(c->cfl > 0.0) || c->cfl * std::sqrt((double)c->dim) > 1.0) return fail(PIC_E_ARG, "cfl must satisfy 0 < c <= 1/sqrt(D)");
+    int blk = c->block ? c->block : 256;
+    if (blk < 64 || blk > 1024 || blk % 64) return fail(PIC_E_ARG, "block must be a multiple of 64 in 64..1024");
+    for (int d = 0; d < 3; ++d) {
+        if (d < c->dim) {
+            if (c->tile[d] < 2 || c->tile[d] % 2) return fail(PIC_E_ARG, "tile[%d] must be even and >= 2", d);
+        } else if (c->tile[d] != 1) {
+            return fail(PIC_E_ARG, "tile[%d] must be 1 beyond dim", d);
+        }
+    }
+    for (int b = 0; b < c->n_boxes; ++b)
+        for (int d = 0; d < c->dim; ++d) {
+            int n = c->box_cells[3 * b + d];
+            if (n < c->tile[d] || n % c->tile[d]) return fail(PIC_E_ARG, "tile[%d]=%d does not divide box %d (n=%d)", d, c->tile[d], b, n);
+        }
+    return PIC_OK;
+}
+
+pic_status make_layout(const pic_config *c, const int64_t *counts, Layout &L)
+{
+    pic_status st = check_config(c);
+    if (st) return st;
+    if (!counts) return fail(PIC_E_ARG, "counts required");
+    const int D = c->dim, ns = c->n_species, nb = c->n_boxes;
+    const int64_t w = c->precision == PIC_FP64 ? 8 : 4;
+    const int *T = c->tile;
+    int64_t cells = 0, tiles = 0;
+    L.box_cell0.assign(nb, 0);
+    L.box_tile0.assign(nb, 0);
+    L.tiles.clear();
+    L.max_ntb = 0;
+    L.max_count = 1;
+    for (int b = 0; b < nb; ++b) {
+        int n[3], nt[3];
+        for (int d = 0; d < 3; ++d) {
+            n[d] = dims_of(c, b, d);
+            nt[d] = n[d] / T[d];
+        }
+        L.box_cell0[b] = cells;
+        L.box_tile0[b] = tiles;
+        int64_t ntb = (int64_t)nt[0] * nt[1] * nt[2];
+        L.max_ntb = std::max(L.max_ntb, ntb);
+        for (int tz = 0; tz < nt[2]; ++tz)
+            for (int ty = 0; ty < nt[1]; ++ty)
+                for (int tx = 0; tx < nt[0]; ++tx) {
+                    TileDesc td{};
+                    td.box = b;
+                    td.tc[0] = tx, td.tc[1] = ty, td.tc[2] = tz;
+                    for (int d = 0; d < 3; ++d) td.nt[d] = nt[d], td.n[d] = n[d];
+                    td.cell0 = cells;
+                    td.tile0 = (int32_t)tiles;
+                    L.tiles.push_back(td);
+                }
+        cells += (int64_t)n[0] * n[1] * n[2];
+        tiles += ntb;
+        for (int s = 0; s < ns; ++s) {
+            if (counts[b * ns + s] < 0) return fail(PIC_E_ARG, "negative particle count");
+            L.max_count = std::max(L.max_count, counts[b * ns + s]);
+        }
+    }
+    if (L.max_ntb > 32768) return fail(PIC_E_ARG, "a box has %lld tiles; at most 32768 are supported", (long long)L.max_ntb);
+    if (tiles > INT32_MAX / 8) return fail(PIC_E_ARG, "too many tiles");
+    // segment capacities
+    double factor = c->capacity_factor > 0 ? c->capacity_factor : 1.25;
+    L.seg_off.assign(tiles * ns, 0);
+    L.seg_cap.assign(tiles * ns, 0);
+    int64_t cap_total = 0, max_cap = 0;
+    std::vector<int64_t> load(tiles, 0);
+    for (int64_t t = 0; t < tiles; ++t) {
+        const int b = L.tiles[t].box;
+        const int64_t ntb = (int64_t)L.tiles[t].nt[0] * L.tiles[t].nt[1] * L.tiles[t].nt[2];
+        for (int s = 0; s < ns; ++s) {
+            int64_t cap;
+            if (c->tile_capacity) {
+                cap = round_up(std::max<int64_t>(c->tile_capacity[t * ns + s], 64), 64);
+            } else {
+                double expect = (double)counts[b * ns + s] / (double)ntb;
+                cap = round_up((int64_t)std::ceil(factor * expect) + 64, 64);
+            }
+            if (cap > INT32_MAX / 2) return fail(PIC_E_ARG, "segment capacity too large");
+            L.seg_off[t * ns + s] = cap_total;
+            L.seg_cap[t * ns + s] = (int32_t)cap;
+            cap_total += cap;
+            max_cap = std::max(max_cap, cap);
+            load[t] += cap;
+        }
+    }
+    // tile visiting order: heaviest first (stable), so that the largest
+    // tiles are dispatched first and the tail is made of small ones
+    L.order.resize(tiles);
+    for (int64_t t = 0; t < tiles; ++t) L.order[t] = (int32_t)t;
+    std::stable_sort(L.order.begin(), L.order.end(), [&](int32_t a, int32_t b) { return load[a] > load[b]; });
+    const int64_t obcap = c->outbox_capacity > 0 ? round_up(c->outbox_capacity, 64)
+                                                 : round_up(std::max<int64_t>(256, max_cap / 4), 64);
+    int64_t cb = 1, rb = 1;
+    for (int d = 0; d < D; ++d) {
+        cb *= T[d] + 3;
+        rb *= T[d] + 1;
+    }
+    L.jblk_cells = cb;
+    L.rblk_cells = rb;
+    L.nchunks_max = std::min<int64_t>(2048, std::max<int64_t>(1, (L.max_count + 4095) / 4096));
+
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        uint64_t o = off;
+        off = align256(off + std::max<uint64_t>(bytes, 1));
+        return o;
+    };
+    pic_layout &P = L.pub;
+    memset(&P, 0, sizeof P);
+    P.off_E = take(3 * cells * w);
+    P.off_B = take(3 * cells * w);
+    P.off_J = take(3 * cells * w);
+    P.off_pos = take(D * cap_total * w);
+    P.off_u = take(3 * cap_total * w);
+    P.off_xold = take(D * cap_total * w);
+    P.off_seg_offset = take(tiles * ns * 8);
+    P.off_seg_capacity = take(tiles * ns * 4);
+    P.off_seg_count = take(tiles * ns * 4);
+    P.off_error = take(4);
+    P.off_flags = take(8);
+    L.off_tmp = take((D + 3) * cap_total * w);
+    L.off_jblk = take(tiles * 3 * cb * w);
+    L.off_rblk = take(tiles * rb * 8);
+    L.off_part = take(tiles * pic::NPART * 8);
+    L.off_ob_pos = take(tiles * ns * obcap * D * w);
+    L.off_ob_u = take(tiles * ns * obcap * 3 * w);
+    L.off_ob_dir = take(tiles * ns * obcap * 4);
+    L.off_ob_cnt = take(tiles * ns * 4);
+    L.off_tiles = take(tiles * sizeof(TileDesc));
+    L.off_charge = take(nb * ns * w);
+    L.off_qm = take(nb * ns * w);
+    L.off_mass = take(nb * ns * 8);
+    L.off_order = take(tiles * 4);
+    L.off_queue = take(4);
+    L.off_key = take(L.max_count * 4);
+    L.off_xl = take(D * L.max_count * w);
+    L.off_hist = take(L.nchunks_max * L.max_ntb * 4);
+    P.total_bytes = off;
+    P.cells_total = cells;
+    P.tiles_total = tiles;
+    P.capacity_total = cap_total;
+    P.outbox_capacity = obcap;
+    P.elem_bytes = (int32_t)w;
+    return PIC_OK;
+}
+
+}  // namespace
+
+struct pic_ctx {
+    int D, prec, ns, nb, block;
+    int T[3];
+    double c;
+    Layout L;
+    hipStream_t stream;
+    uint8_t *ws;
+    std::vector<double> mass;
+    int state;          // 0 ready, 1 unfused push done, 2 fused push done, 3 unfused deposit done
+};
+
+namespace {
+
+template <typename R>
+Params<R> params(pic_ctx *x)
+{
+    Params<R> p{};
+    const Layout &L = x->L;
+    uint8_t *ws = x->ws;
+    p.tiles = reinterpret_cast<const TileDesc *>(ws + L.off_tiles);
+    p.ntiles = (int32_t)L.pub.tiles_total;
+    p.nspecies = x->ns;
+    for (int d = 0; d < 3; ++d) p.T[d] = x->T[d];
+    p.c = (R)x->c;
+    p.charge = reinterpret_cast<const R *>(ws + L.off_charge);
+    p.qm = reinterpret_cast<const R *>(ws + L.off_qm);
+    p.E = reinterpret_cast<R *>(ws + L.pub.off_E);
+    p.B = reinterpret_cast<R *>(ws + L.pub.off_B);
+    p.J = reinterpret_cast<R *>(ws + L.pub.off_J);
+    p.cells_total = L.pub.cells_total;
+    p.pos = reinterpret_cast<R *>(ws + L.pub.off_pos);
+    p.u = reinterpret_cast<R *>(ws + L.pub.off_u);
+    p.xold = reinterpret_cast<R *>(ws + L.pub.off_xold);
+    p.cap_total = L.pub.capacity_total;
+    p.seg_off = reinterpret_cast<const int64_t *>(ws + L.pub.off_seg_offset);
+    p.seg_cap = reinterpret_cast<const int32_t *>(ws + L.pub.off_seg_capacity);
+    p.seg_cnt = reinterpret_cast<int32_t *>(ws + L.pub.off_seg_count);
+    p.jblk = reinterpret_cast<R *>(ws + L.off_jblk);
+    p.ob_pos = reinterpret_cast<R *>(ws + L.off_ob_pos);
+    p.ob_u = reinterpret_cast<R *>(ws + L.off_ob_u);
+    p.ob_dir = reinterpret_cast<int32_t *>(ws + L.off_ob_dir);
+    p.ob_cnt = reinterpret_cast<int32_t *>(ws + L.off_ob_cnt);
+    p.ob_cap = L.pub.outbox_capacity;
+    p.tmp = reinterpret_cast<R *>(ws + L.off_tmp);
+    p.err = reinterpret_cast<int32_t *>(ws + L.pub.off_error);
+    p.nearface = reinterpret_cast<unsigned long long *>(ws + L.pub.off_flags);
+    p.queue = reinterpret_cast<int32_t *>(ws + L.off_queue);
+    p.order = reinterpret_cast<const int32_t *>(ws + L.off_order);
+    return p;
+}
+
+template <typename K>
+pic_status set_lds(K kernel, size_t bytes)
+{
+    if (bytes > 160 * 1024) return fail(PIC_E_ARG, "tile needs %zu bytes of LDS (max 163840); use a smaller tile", bytes);
+    if (bytes > 64 * 1024)
+        HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)bytes));
+    return PIC_OK;
+}
+
+template <typename T>
+pic_status fill(pic_ctx *x, T *p, int64_t n, T v)
+{
+    if (n <= 0) return PIC_OK;
+    int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(pic::k_fill<T>, dim3(grid), dim3(256), 0, x->stream, p, n, v);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
+template <typename R, int D>
+struct Impl {
+    static size_t push_lds(pic_ctx *x, bool fused)
+    {
+        int64_t fbn = 1, cbn = 1;
+        for (int d = 0; d < D; ++d) {
+            fbn *= x->T[d] + 2;
+            cbn *= x->T[d] + 3;
+        }
+        return (6 * fbn + (fused ? 3 * cbn : 0)) * sizeof(R) + 2 * pic::MAX_WAVES * sizeof(int);
+    }
+
+    static pic_status fdtd(pic_ctx *x, int phase)
+    {
+        Params<R> p = params<R>(x);
+        dim3 g((unsigned)x->L.pub.tiles_total), b(256);
+        const R c = (R)x->c;
+        switch (phase) {
+        case PIC_HALF_B: hipLaunchKernelGGL((pic::k_field<R, D, 0>), g, b, 0, x->stream, p, R(0.5) * c); break;
+        case PIC_CURL_E: hipLaunchKernelGGL((pic::k_field<R, D, 1>), g, b, 0, x->stream, p, c); break;
+        case PIC_ADD_J: hipLaunchKernelGGL((pic::k_field<R, D, 2>), g, b, 0, x->stream, p, c); break;
+        case PIC_CURL_E_ADD_J: hipLaunchKernelGGL((pic::k_field<R, D, 3>), g, b, 0, x->stream, p, c); break;
+        default: return fail(PIC_E_ARG, "unknown fdtd phase %d", phase);
+        }
+        HIP_OK(hipGetLastError());
+        return PIC_OK;
+    }
+
+    static pic_status push(pic_ctx *x, bool fused)
+    {
+        Params<R> p = params<R>(x);
+        size_t lds = push_lds(x, fused);
+        dim3 g((unsigned)x->L.pub.tiles_total), b(x->block);
+        if (fused) {
+            pic_status st = set_lds(pic::k_push<R, D, true>, lds);
+            if (st) return st;
+            hipLaunchKernelGGL((pic::k_push<R, D, true>), g, b, lds, x->stream, p);
+        } else {
+            pic_status st = set_lds(pic::k_push<R, D, false>, lds);
+            if (st) return st;
+            hipLaunchKernelGGL((pic::k_push<R, D, false>), g, b, lds, x->stream, p);
+        }
+        HIP_OK(hipGetLastError());
+        return PIC_OK;
+    }
+
+    static pic_status deposit(pic_ctx *x, bool unfused_part)
+    {
+        Params<R> p = params<R>(x);
+        dim3 g((unsigned)x->L.pub.tiles_total);
+        if (unfused_part) {
+            size_t lds = 3 * x->L.jblk_cells * sizeof(R);
+            pic_status st = set_lds(pic::k_deposit<R, D>, lds);
+            if (st) return st;
+            hipLaunchKernelGGL((pic::k_deposit<R, D>), g, dim3(x->block), lds, x->stream, p);
+            HIP_OK(hipGetLastError());
+        }
+        hipLaunchKernelGGL((pic::k_fold<R, D>), g, dim3(256), 0, x->stream, p);
+        HIP_OK(hipGetLastError());
+        return PIC_OK;
+    }
+
+    static pic_status migrate(pic_ctx *x, bool need_out, bool need_in, bool sort)
+    {
+        Params<R> p = params<R>(x);
+        dim3 g((unsigned)x->L.pub.tiles_total);
+        if (need_out) {
+            hipLaunchKernelGGL((pic::k_migrate_out<R, D>), g, dim3(x->block), 0, x->stream, p);
+            HIP_OK(hipGetLastError());
+        }
+        if (need_in) {
+            hipLaunchKernelGGL((pic::k_migrate_in<R, D>), g, dim3(x->block), 0, x->stream, p);
+            HIP_OK(hipGetLastError());
+        }
+        if (sort) {
+            int ncell = x->T[0] * x->T[1] * x->T[2];
+            size_t lds = (size_t)(4 + 1) * ncell * sizeof(int);
+            pic_status st = set_lds(pic::k_cell_sort<R, D>, lds);
+            if (st) return st;
+            st = fill<unsigned long long>(x, p.nearface, 1, 0ull);
+            if (st) return st;
+            hipLaunchKernelGGL((pic::k_cell_sort<R, D>), g, dim3(256), lds, x->stream, p);
+            HIP_OK(hipGetLastError());
+        }
+        return PIC_OK;
+    }
+
+    static pic_status init(pic_ctx *x, const int64_t *counts, const pic_init_data *in)
+    {
+        Params<R> p = params<R>(x);
+        const Layout &L = x->L;
+        uint8_t *ws = x->ws;
+        int32_t *key = reinterpret_cast<int32_t *>(ws + L.off_key);
+        R *xl = reinterpret_cast<R *>(ws + L.off_xl);
+        int32_t *hist = reinterpret_cast<int32_t *>(ws + L.off_hist);
+        pic_status st = fill<int32_t>(x, p.seg_cnt, L.pub.tiles_total * x->ns, 0);
+        if (!st) st = fill<int32_t>(x, p.ob_cnt, L.pub.tiles_total * x->ns, 0);
+        if (!st) st = fill<R>(x, p.J, 3 * L.pub.cells_total, R(0));
+        if (!st) st = fill<R>(x, p.E, 3 * L.pub.cells_total, R(0));
+        if (!st) st = fill<R>(x, p.B, 3 * L.pub.cells_total, R(0));
+        if (!st) st = fill<R>(x, p.jblk, L.pub.tiles_total * 3 * L.jblk_cells, R(0));
+        if (st) return st;
+        for (int b = 0; b < x->nb; ++b) {
+            const TileDesc &t0 = L.tiles[L.box_tile0[b]];
+            const int64_t cells = (int64_t)t0.n[0] * t0.n[1] * t0.n[2];
+            int grid = (int)std::min<int64_t>((3 * cells + 255) / 256, 8192);
+            if (in->E && in->E[b])
+                hipLaunchKernelGGL((pic::k_load_field<R>), dim3(grid), dim3(256), 0, x->stream, p.E, L.pub.cells_total,
+                                   L.box_cell0[b], in->E[b], cells);
+            if (in->B && in->B[b])
+                hipLaunchKernelGGL((pic::k_load_field<R>), dim3(grid), dim3(256), 0, x->stream, p.B, L.pub.cells_total,
+                                   L.box_cell0[b], in->B[b], cells);
+            HIP_OK(hipGetLastError());
+            for (int s = 0; s < x->ns; ++s) {
+                const int64_t count = counts[b * x->ns + s];
+                if (count == 0) continue;
+                if (!in->pos || !in->u || !in->pos[b * x->ns + s] || !in->u[b * x->ns + s])
+                    return fail(PIC_E_ARG, "missing particle data for box %d species %d", b, s);
+                pic::BinGeom g{};
+                for (int d = 0; d < 3; ++d) {
+                    g.n[d] = t0.n[d];
+                    g.T[d] = x->T[d];
+                    g.nt[d] = t0.nt[d];
+                }
+                g.ntb = t0.nt[0] * t0.nt[1] * t0.nt[2];
+                g.count = count;
+                g.nchunks = (int32_t)std::min<int64_t>(L.nchunks_max, std::max<int64_t>(1, (count + 4095) / 4096));
+                g.chunk = (int32_t)((count + g.nchunks - 1) / g.nchunks);
+                int kgrid = (int)std::min<int64_t>((count + 255) / 256, 16384);
+                hipLaunchKernelGGL((pic::k_bin_keys<R, D>), dim3(kgrid), dim3(256), 0, x->stream, g, in->pos[b * x->ns + s],
+                                   key, xl, p.err, p.nearface);
+                size_t lds = (size_t)g.ntb * sizeof(int);
+                st = set_lds(pic::k_bin_hist, lds);
+                if (st) return st;
+                hipLaunchKernelGGL(pic::k_bin_hist, dim3(g.nchunks), dim3(256), lds, x->stream, g, key, hist);
+                hipLaunchKernelGGL(pic::k_bin_scan, dim3((g.ntb + 255) / 256), dim3(256), 0, x->stream, g, hist, p.seg_cnt,
+                                   p.seg_cap, (int)L.box_tile0[b], x->ns, s, p.err);
+                st = set_lds(pic::k_bin_scatter<R, D>, lds);
+                if (st) return st;
+                hipLaunchKernelGGL((pic::k_bin_scatter<R, D>), dim3(g.nchunks), dim3(64), lds, x->stream, g, key, xl,
+                                   in->u[b * x->ns + s], hist, p, (int)L.box_tile0[b], s);
+                HIP_OK(hipGetLastError());
+            }
+        }
+        return PIC_OK;
+    }
+
+    static pic_status diag(pic_ctx *x, pic_diag *out)
+    {
+        Params<R> p = params<R>(x);
+        const Layout &L = x->L;
+        double *part = reinterpret_cast<double *>(x->ws + L.off_part);
+        double *rblk = reinterpret_cast<double *>(x->ws + L.off_rblk);
+        const double *mass = reinterpret_cast<const double *>(x->ws + L.off_mass);
+        size_t lds = L.rblk_cells * sizeof(double);
+        pic_status st = set_lds(pic::k_diag_tile<R, D>, lds);
+        if (st) return st;
+        dim3 g((unsigned)L.pub.tiles_total);
+        hipLaunchKernelGGL((pic::k_diag_tile<R, D>), g, dim3(256), lds, x->stream, p, mass, part, rblk);
+        hipLaunchKernelGGL((pic::k_diag_gauss<R, D>), g, dim3(256), 0, x->stream, p, part, rblk);
+        HIP_OK(hipGetLastError());
+        std::vector<double> h(L.pub.tiles_total * pic::NPART);
+        HIP_OK(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, x->stream));
+        unsigned long long nf = 0;
+        HIP_OK(hipMemcpyAsync(&nf, p.nearface, sizeof nf, hipMemcpyDeviceToHost, x->stream));
+        HIP_OK(hipStreamSynchronize(x->stream));
+        memset(out, 0, sizeof *out);
+        for (int64_t t = 0; t < L.pub.tiles_total; ++t) {
+            const double *o = &h[t * pic::NPART];
+            out->field_energy += o[0];
+            out->divb_max = std::max(out->divb_max, o[1]);
+            out->kinetic_energy += o[2];
+            out->particles += (int64_t)o[3];
+            out->gauss_max = std::max(out->gauss_max, o[4]);
+            out->charge_total += o[5];
+        }
+        out->near_face = (int64_t)nf;
+        return PIC_OK;
+    }
+};
+
+#define PIC_DISPATCH(ctx, CALL)                                      \
+    do {                                                             \
+        if ((ctx)->prec == PIC_FP32) {                               \
+            switch ((ctx)->D) {                                      \
+            case 1: return Impl<float, 1>::CALL;                     \
+            case 2: return Impl<float, 2>::CALL;                     \
+            default: return Impl<float, 3>::CALL;                    \
+            }                                                        \
+        } else {                                                     \
+            switch ((ctx)->D) {                                      \
+            case 1: return Impl<double, 1>::CALL;                    \
+            case 2: return Impl<double, 2>::CALL;                    \
+            default: return Impl<double, 3>::CALL;                   \
+            }                                                        \
+        }                                                            \
+    } while (0)
+
+pic_status do_init(pic_ctx *x, const int64_t *counts, const pic_init_data *in) { PIC_DISPATCH(x, init(x, counts, in)); }
+pic_status do_fdtd(pic_ctx *x, int phase) { PIC_DISPATCH(x, fdtd(x, phase)); }
+pic_status do_push(pic_ctx *x, bool fused) { PIC_DISPATCH(x, push(x, fused)); }
+pic_status do_deposit(pic_ctx *x, bool unfused) { PIC_DISPATCH(x, deposit(x, unfused)); }
+pic_status do_migrate(pic_ctx *x, bool out, bool in, bool sort) { PIC_DISPATCH(x, migrate(x, out, in, sort)); }
+pic_status do_diag(pic_ctx *x, pic_diag *o) { PIC_DISPATCH(x, diag(x, o)); }
+
+template <typename R>
+pic_status upload_tables(pic_ctx *x, const pic_config *cfg)
+{
+    const Layout &L = x->L;
+    uint8_t *ws = x->ws;
+    const int n = x->nb * x->ns;
+    std::vector<R> ch(n), qm(n);
+    for (int i = 0; i < n; ++i) {
+        ch[i] = (R)cfg->charge[i];
+        qm[i] = (R)cfg->qm[i];
+    }
+    x->mass.assign(cfg->mass, cfg->mass + n);
+    HIP_OK(hipMemcpy(ws + L.off_charge, ch.data(), n * sizeof(R), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(ws + L.off_qm, qm.data(), n * sizeof(R), hipMemcpyHostToDevice));
+    return PIC_OK;
+}
+
+pic_status read_error(pic_ctx *x, int32_t *bits)
+{
+    int32_t *err = reinterpret_cast<int32_t *>(x->ws + x->L.pub.off_error);
+    HIP_OK(hipMemcpyAsync(bits, err, sizeof(int32_t), hipMemcpyDeviceToHost, x->stream));
+    HIP_OK(hipStreamSynchronize(x->stream));
+    if (*bits) {
+        pic_status st = fill<int32_t>(x, err, 1, 0);
+        if (st) return st;
+        HIP_OK(hipStreamSynchronize(x->stream));
+    }
+    return PIC_OK;
+}
+
+pic_status error_status(int32_t bits)
+{
+    pic_status st = 0;
+    if (bits & pic::ERR_CAPACITY) st |= PIC_E_CAPACITY;
+    if (bits & pic::ERR_CFL) st |= PIC_E_CFL;
+    if (bits & pic::ERR_NONFINITE) st |= PIC_E_NONFINITE;
+    if (bits & pic::ERR_OUT_OF_TILE) st |= PIC_E_OUT_OF_TILE;
+    if (st) fail(st, "device error bits 0x%x", bits);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+pic_status pic_query(const pic_config *cfg, const int64_t *counts, pic_layout *out)
+{
+    if (!out) return fail(PIC_E_ARG, "null output");
+    Layout L;
+    pic_status st = make_layout(cfg, counts, L);
+    if (st) return st;
+    *out = L.pub;
+    return PIC_OK;
+}
+
+pic_status pic_init_tiles(const pic_config *cfg, const int64_t *counts, void *workspace, uint64_t workspace_bytes,
+                          const pic_init_data *init, void *hip_stream, pic_ctx **out)
+{
+    if (!out || !init) return fail(PIC_E_ARG, "null argument");
+    *out = nullptr;
+    pic_ctx *x = new pic_ctx();
+    pic_status st = make_layout(cfg, counts, x->L);
+    if (st) {
+        delete x;
+        return st;
+    }
+    if (!workspace || workspace_bytes < x->L.pub.total_bytes || (reinterpret_cast<uintptr_t>(workspace) & 255)) {
+        delete x;
+        return fail(PIC_E_ARG, "workspace must be 256-byte aligned and hold %llu bytes",
+                    (unsigned long long)x->L.pub.total_bytes);
+    }
+    x->D = cfg->dim;
+    x->prec = cfg->precision;
+    x->ns = cfg->n_species;
+    x->nb = cfg->n_boxes;
+    x->block = cfg->block ? cfg->block : 256;
+    for (int d = 0; d < 3; ++d) x->T[d] = cfg->tile[d];
+    x->c = cfg->cfl;
+    x->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    x->ws = reinterpret_cast<uint8_t *>(workspace);
+    x->state = 0;
+    const Layout &L = x->L;
+    auto cleanup = [&](pic_status s) {
+        delete x;
+        return s;
+    };
+#define INIT_HIP(expr)                                                                           \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess) return cleanup(fail(PIC_E_HIP, "%s: %s", #expr, hipGetErrorString(e_))); \
+    } while (0)
+    INIT_HIP(hipStreamSynchronize(x->stream));
+    INIT_HIP(hipMemcpy(x->ws + L.off_tiles, L.tiles.data(), L.tiles.size() * sizeof(TileDesc), hipMemcpyHostToDevice));
+    INIT_HIP(hipMemcpy(x->ws + L.pub.off_seg_offset, L.seg_off.data(), L.seg_off.size() * 8, hipMemcpyHostToDevice));
+    INIT_HIP(hipMemcpy(x->ws + L.pub.off_seg_capacity, L.seg_cap.data(), L.seg_cap.size() * 4, hipMemcpyHostToDevice));
+    INIT_HIP(hipMemcpy(x->ws + L.off_order, L.order.data(), L.order.size() * 4, hipMemcpyHostToDevice));
+    INIT_HIP(hipMemcpy(x->ws + L.off_mass, cfg->mass, (size_t)x->nb * x->ns * 8, hipMemcpyHostToDevice));
+    st = x->prec == PIC_FP32 ? upload_tables<float>(x, cfg) : upload_tables<double>(x, cfg);
+    if (st) return cleanup(st);
+    if ((st = fill<int32_t>(x, reinterpret_cast<int32_t *>(x->ws + L.pub.off_error), 1, 0))) return cleanup(st);
+    if ((st = fill<unsigned long long>(x, reinterpret_cast<unsigned long long *>(x->ws + L.pub.off_flags), 1, 0ull)))
+        return cleanup(st);
+    if ((st = do_init(x, counts, init))) return cleanup(st);
+    int32_t bits = 0;
+    if ((st = read_error(x, &bits))) return cleanup(st);
+    if (bits) return cleanup(error_status(bits));
+#undef INIT_HIP
+    *out = x;
+    return PIC_OK;
+}
+
+pic_status pic_fdtd_step(pic_ctx *x, int32_t phase)
+{
+    if (!x) return fail(PIC_E_ARG, "null context");
+    return do_fdtd(x, phase);
+}
+
+pic_status pic_push_interp(pic_ctx *x, uint32_t flags)
+{
+    if (!x) return fail(PIC_E_ARG, "null context");
+    if (x->state != 0) return fail(PIC_E_STATE, "push called before the previous push was deposited and migrated");
+    const bool fused = flags & PIC_FUSED;
+    pic_status st = do_push(x, fused);
+    if (st) return st;
+    x->state = fused ? 2 : 1;
+    return PIC_OK;
+}
+
+pic_status pic_deposit_current(pic_ctx *x, uint32_t flags)
+{
+    (void)flags;
+    if (!x) return fail(PIC_E_ARG, "null context");
+    if (x->state == 1) {
+        pic_status st = do_deposit(x, true);
+        if (st) return st;
+        x->state = 3;
+        return PIC_OK;
+    }
+    if (x->state == 2) return do_deposit(x, false);
+    return fail(PIC_E_STATE, "deposit needs a preceding push");
+}
+
+pic_status pic_sort_migrate(pic_ctx *x, uint32_t flags)
+{
+    if (!x) return fail(PIC_E_ARG, "null context");
+    if (x->state == 1) return fail(PIC_E_STATE, "deposit the current of an unfused push before migrating");
+    const bool sort = flags & PIC_SORT_CELLS;
+    pic_status st;
+    if (x->state == 3) st = do_migrate(x, true, true, sort);        // unfused push: out + in
+    else if (x->state == 2) st = do_migrate(x, false, true, sort);  // fused push packed already
+    else st = sort ? do_migrate(x, false, false, true) : PIC_OK;    // nothing moved: sort only
+    if (st) return st;
+    x->state = 0;
+    return PIC_OK;
+}
+
+pic_status pic_step(pic_ctx *x, uint32_t flags)
+{
+    pic_status st;
+    if ((st = pic_fdtd_step(x, PIC_HALF_B))) return st;
+    if ((st = pic_push_interp(x, flags))) return st;
+    if ((st = pic_fdtd_step(x, PIC_HALF_B))) return st;
+    if ((st = pic_deposit_current(x, flags))) return st;
+    if ((st = pic_fdtd_step(x, PIC_CURL_E_ADD_J))) return st;
+    return pic_sort_migrate(x, flags);
+}
+
+pic_status pic_error(pic_ctx *x)
+{
+    if (!x) return fail(PIC_E_ARG, "null context");
+    int32_t bits = 0;
+    pic_status st = read_error(x, &bits);
+    if (st) return st;
+    return error_status(bits);
+}
+
+pic_status pic_diagnostics(pic_ctx *x, pic_diag *out)
+{
+    if (!x || !out) return fail(PIC_E_ARG, "null argument");
+    pic_status st = do_diag(x, out);
+    if (st) return st;
+    int32_t bits = 0;
+    if ((st = read_error(x, &bits))) return st;
+    out->error_bits = bits;
+    return error_status(bits);
+}
+
+pic_status pic_destroy(pic_ctx *x)
+{
+    delete x;
+    return PIC_OK;
+}
+
+const char *pic_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

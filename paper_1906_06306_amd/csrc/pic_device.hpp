@@ -1,0 +1,365 @@
+// Device-side building blocks of the relativistic PIC step for gfx950.
+//
+// Everything here is templated on the working precision R (float, double)
+// and on the number of spatial dimensions D, so that the hot loops are
+// straight-line code.  Particles carry positions relative to their tile
+// centre; tiles are staged in LDS with a halo, so that interpolation reads
+// and deposit atomics never leave the work-group's LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pic {
+
+// ---------------------------------------------------------------- tables
+
+// One entry per tile of every box.
+struct TileDesc {
+    int32_t box;
+    int32_t tc[3];      // tile coordinates inside the box
+    int32_t nt[3];      // tiles per dimension of the box
+    int32_t n[3];       // cells per dimension of the box
+    int64_t cell0;      // offset of the box's first cell in the field planes
+    int32_t tile0;      // global id of the box's tile (0,0,0)
+    int32_t pad;
+};
+
+// Launch-wide constants of the particle and field kernels.
+template <typename R>
+struct Params {
+    const TileDesc *tiles;
+    int32_t ntiles;
+    int32_t nspecies;
+    int32_t T[3];
+    int32_t pad0;
+    R c;                      // Courant number
+    const R *charge;          // [box][species]
+    const R *qm;              // [box][species] App. C factor s
+    R *E, *B, *J;             // [3][cells_total]
+    int64_t cells_total;
+    R *pos, *u, *xold;        // [D|3][cap_total]
+    int64_t cap_total;
+    const int64_t *seg_off;   // [tile][species]
+    const int32_t *seg_cap;
+    int32_t *seg_cnt;
+    R *jblk;                  // [tile][3][JV]
+    R *ob_pos, *ob_u;         // [tile*species][D|3][ob_cap]
+    int32_t *ob_dir;          // [tile*species][ob_cap]
+    int32_t *ob_cnt;          // [tile*species]
+    int64_t ob_cap;
+    R *tmp;                   // sort staging [(D+3)][cap_total]
+    int32_t *err;             // latched error bits
+    unsigned long long *nearface;
+    int32_t *queue;           // work counter of the persistent walker
+    const int32_t *order;     // tile visiting order of the persistent walker
+};
+
+enum : int32_t { ERR_CAPACITY = 1, ERR_CFL = 2, ERR_NONFINITE = 4, ERR_OUT_OF_TILE = 8 };
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ int wrapi(int i, int n)
+{
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+template <int D>
+__device__ __forceinline__ int ext(const int32_t T[3], int d, int halo)
+{
+    return d < D ? T[d] + halo : 1;
+}
+
+// Number of lanes below this one whose bit is set in mask.
+__device__ __forceinline__ int lanes_below(unsigned long long mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ void latch(int32_t *err, int32_t bits)
+{
+    atomicOr(err, bits);
+}
+
+template <typename R>
+__device__ __forceinline__ void lds_add(R *p, R v)
+{
+    atomicAdd(p, v);
+}
+
+// Field halo block in LDS: local cells -1..T per grid dimension.
+template <int D>
+struct FieldBox {
+    int e0, e1, e2;   // extents
+    int n;            // cells in the block
+    __device__ FieldBox(const int32_t T[3])
+    {
+        e0 = ext<D>(T, 0, 2);
+        e1 = ext<D>(T, 1, 2);
+        e2 = ext<D>(T, 2, 2);
+        n = e0 * e1 * e2;
+    }
+};
+
+// Current halo block: local cells -1..T+1 per grid dimension.
+template <int D>
+struct CurBox {
+    int e0, e1, e2;
+    int n;
+    __device__ CurBox(const int32_t T[3])
+    {
+        e0 = ext<D>(T, 0, 3);
+        e1 = ext<D>(T, 1, 3);
+        e2 = ext<D>(T, 2, 3);
+        n = e0 * e1 * e2;
+    }
+};
+
+// Copy E and B of the tile plus a one-cell halo into LDS (periodic wrap).
+// sF layout: [6][fb.n], component order Ex Ey Ez Bx By Bz.
+template <typename R, int D>
+__device__ void stage_fields(const Params<R> &p, const TileDesc &td, R *sF, const FieldBox<D> &fb)
+{
+    const int n0 = td.n[0], n1 = td.n[1], n2 = td.n[2];
+    for (int k = threadIdx.x; k < fb.n; k += blockDim.x) {
+        int lx = k % fb.e0, ly = (k / fb.e0) % fb.e1, lz = k / (fb.e0 * fb.e1);
+        int gx = D > 0 ? wrapi(td.tc[0] * p.T[0] + lx - 1, n0) : 0;
+        int gy = D > 1 ? wrapi(td.tc[1] * p.T[1] + ly - 1, n1) : 0;
+        int gz = D > 2 ? wrapi(td.tc[2] * p.T[2] + lz - 1, n2) : 0;
+        int64_t g = td.cell0 + gx + (int64_t)n0 * (gy + (int64_t)n1 * gz);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            sF[m * fb.n + k] = p.E[m * p.cells_total + g];
+            sF[(3 + m) * fb.n + k] = p.B[m * p.cells_total + g];
+        }
+    }
+}
+
+// ---------------------------------------------------------- interpolation
+
+// Per-particle interpolation state: for each grid dimension the LDS base
+// index and weight of a node-centred (offset 0) and a half-cell (offset
+// 1/2) sub-lattice.
+template <typename R, int D>
+struct Stencil {
+    int bn[3], bh[3];
+    R wn[3], wh[3];
+};
+
+template <typename R, int D>
+__device__ __forceinline__ void make_stencil(const R x[3], const int32_t T[3], Stencil<R, D> &s)
+{
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        R fl = floor(x[d]);
+        int ci = (int)fl + T[d] / 2;      // cell in 0..T-1
+        R f = x[d] - fl;
+        s.bn[d] = ci + 1;                  // LDS offset of local cell -1 is 0
+        s.wn[d] = f;
+        bool up = f >= R(0.5);
+        s.bh[d] = up ? ci + 1 : ci;
+        s.wh[d] = up ? f - R(0.5) : f + R(0.5);
+    }
+}
+
+// Linear interpolation of component COMP (0..5 = Ex..Bz) from its own
+// staggered sub-lattice: per dimension the half-cell lattice is used where
+// the component is staggered by 1/2.
+template <typename R, int D, int COMP>
+__device__ __forceinline__ R interp_comp(const R *__restrict__ F, int s1, int s2, const Stencil<R, D> &st)
+{
+    constexpr bool h0 = COMP == 0 || COMP == 4 || COMP == 5;
+    constexpr bool h1 = COMP == 1 || COMP == 3 || COMP == 5;
+    constexpr bool h2 = COMP == 2 || COMP == 3 || COMP == 4;
+    int b = h0 ? st.bh[0] : st.bn[0];
+    R w0 = h0 ? st.wh[0] : st.wn[0];
+    if constexpr (D == 1) {
+        return F[b] * (R(1) - w0) + F[b + 1] * w0;
+    } else {
+        b += (h1 ? st.bh[1] : st.bn[1]) * s1;
+        R w1 = h1 ? st.wh[1] : st.wn[1];
+        if constexpr (D == 2) {
+            R a0 = F[b] * (R(1) - w0) + F[b + 1] * w0;
+            R a1 = F[b + s1] * (R(1) - w0) + F[b + s1 + 1] * w0;
+            return a0 * (R(1) - w1) + a1 * w1;
+        } else {
+            b += (h2 ? st.bh[2] : st.bn[2]) * s2;
+            R w2 = h2 ? st.wh[2] : st.wn[2];
+            R a00 = F[b] * (R(1) - w0) + F[b + 1] * w0;
+            R a10 = F[b + s1] * (R(1) - w0) + F[b + s1 + 1] * w0;
+            R a01 = F[b + s2] * (R(1) - w0) + F[b + s2 + 1] * w0;
+            R a11 = F[b + s1 + s2] * (R(1) - w0) + F[b + s1 + s2 + 1] * w0;
+            R c0 = a00 * (R(1) - w1) + a10 * w1;
+            R c1 = a01 * (R(1) - w1) + a11 * w1;
+            return c0 * (R(1) - w2) + c1 * w2;
+        }
+    }
+}
+
+template <typename R, int D>
+__device__ __forceinline__ void interp_all(const R *sF, const FieldBox<D> &fb, const R x[3], const int32_t T[3],
+                                           R e[3], R b[3])
+{
+    Stencil<R, D> st;
+    make_stencil<R, D>(x, T, st);
+    const int s1 = fb.e0, s2 = fb.e0 * fb.e1;
+    e[0] = interp_comp<R, D, 0>(sF + 0 * fb.n, s1, s2, st);
+    e[1] = interp_comp<R, D, 1>(sF + 1 * fb.n, s1, s2, st);
+    e[2] = interp_comp<R, D, 2>(sF + 2 * fb.n, s1, s2, st);
+    b[0] = interp_comp<R, D, 3>(sF + 3 * fb.n, s1, s2, st);
+    b[1] = interp_comp<R, D, 4>(sF + 4 * fb.n, s1, s2, st);
+    b[2] = interp_comp<R, D, 5>(sF + 5 * fb.n, s1, s2, st);
+}
+
+// ------------------------------------------------------------------ Boris
+
+// Relativistic Boris update (App. C) of u^{n-1/2} -> u^{n+1/2}; velocities
+// inside the update are carried in units of the Courant number.
+template <typename R>
+__device__ __forceinline__ void boris(R u[3], const R e[3], const R b[3], R c, R s)
+{
+    const R hs = R(0.5) * s;
+    R ex = hs * e[0], ey = hs * e[1], ez = hs * e[2];
+    R u1x = c * u[0] + ex, u1y = c * u[1] + ey, u1z = c * u[2] + ez;
+    R g1 = sqrt(R(1) + (u1x * u1x + u1y * u1y + u1z * u1z) / (c * c));
+    R k = s / (R(2) * c * g1);
+    R tx = k * b[0], ty = k * b[1], tz = k * b[2];
+    R f = R(2) / (R(1) + (tx * tx + ty * ty + tz * tz));
+    R u2x = f * (u1x + (u1y * tz - u1z * ty));
+    R u2y = f * (u1y + (u1z * tx - u1x * tz));
+    R u2z = f * (u1z + (u1x * ty - u1y * tx));
+    R u3x = u1x + (u2y * tz - u2z * ty) + ex;
+    R u3y = u1y + (u2z * tx - u2x * tz) + ey;
+    R u3z = u1z + (u2x * ty - u2y * tx) + ez;
+    u[0] = u3x / c;
+    u[1] = u3y / c;
+    u[2] = u3z / c;
+}
+
+// Eq. (fdX): displacement c u / gamma of u^{n+1/2}, all three components.
+template <typename R>
+__device__ __forceinline__ void displacement(const R u[3], R c, R dv[3])
+{
+    R g = sqrt(R(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    dv[0] = c * u[0] / g;
+    dv[1] = c * u[1] / g;
+    dv[2] = c * u[2] / g;
+}
+
+// ----------------------------------------------------------------- ZigZag
+
+// Deposit one straight segment inside one cell into the LDS current block:
+// component m goes to the cell index along m and, along each transverse
+// grid dimension a, to points i_a and i_a+1 with weights 1-W_a and W_a at
+// the segment midpoint; with two transverse dimensions the path average of
+// the product adds sigma_a sigma_b dv_a dv_b / 12.
+template <typename R, int D>
+__device__ __forceinline__ void deposit_segment(R *sJ, const CurBox<D> &cb, const R F[3], const R W[3],
+                                                const R dv[3], const int li[3])
+{
+    const int s1 = cb.e0, s2 = cb.e0 * cb.e1;
+    int base = li[0];
+    if constexpr (D > 1) base += li[1] * s1;
+    if constexpr (D > 2) base += li[2] * s2;
+    R *Jx = sJ, *Jy = sJ + cb.n, *Jz = sJ + 2 * cb.n;
+    if constexpr (D == 1) {
+        lds_add(Jx + base, F[0]);
+        lds_add(Jy + base, F[1] * (R(1) - W[0]));
+        lds_add(Jy + base + 1, F[1] * W[0]);
+        lds_add(Jz + base, F[2] * (R(1) - W[0]));
+        lds_add(Jz + base + 1, F[2] * W[0]);
+    } else if constexpr (D == 2) {
+        lds_add(Jx + base, F[0] * (R(1) - W[1]));
+        lds_add(Jx + base + s1, F[0] * W[1]);
+        lds_add(Jy + base, F[1] * (R(1) - W[0]));
+        lds_add(Jy + base + 1, F[1] * W[0]);
+        R cr = dv[0] * dv[1] / R(12);
+        lds_add(Jz + base, F[2] * ((R(1) - W[0]) * (R(1) - W[1]) + cr));
+        lds_add(Jz + base + 1, F[2] * (W[0] * (R(1) - W[1]) - cr));
+        lds_add(Jz + base + s1, F[2] * ((R(1) - W[0]) * W[1] - cr));
+        lds_add(Jz + base + s1 + 1, F[2] * (W[0] * W[1] + cr));
+    } else {
+        R cyz = dv[1] * dv[2] / R(12);
+        lds_add(Jx + base, F[0] * ((R(1) - W[1]) * (R(1) - W[2]) + cyz));
+        lds_add(Jx + base + s1, F[0] * (W[1] * (R(1) - W[2]) - cyz));
+        lds_add(Jx + base + s2, F[0] * ((R(1) - W[1]) * W[2] - cyz));
+        lds_add(Jx + base + s1 + s2, F[0] * (W[1] * W[2] + cyz));
+        R cxz = dv[0] * dv[2] / R(12);
+        lds_add(Jy + base, F[1] * ((R(1) - W[0]) * (R(1) - W[2]) + cxz));
+        lds_add(Jy + base + 1, F[1] * (W[0] * (R(1) - W[2]) - cxz));
+        lds_add(Jy + base + s2, F[1] * ((R(1) - W[0]) * W[2] - cxz));
+        lds_add(Jy + base + 1 + s2, F[1] * (W[0] * W[2] + cxz));
+        R cxy = dv[0] * dv[1] / R(12);
+        lds_add(Jz + base, F[2] * ((R(1) - W[0]) * (R(1) - W[1]) + cxy));
+        lds_add(Jz + base + 1, F[2] * (W[0] * (R(1) - W[1]) - cxy));
+        lds_add(Jz + base + s1, F[2] * ((R(1) - W[0]) * W[1] - cxy));
+        lds_add(Jz + base + s1 + 1, F[2] * (W[0] * W[1] + cxy));
+    }
+}
+
+// ZigZag deposit (App. D) of one particle moving from x1 to x2 (tile-local,
+// unrebased) with displacement dv (all three components) and charge q.
+// Relay point per grid dimension: min(min(i1,i2)+1, max(max(i1,i2),
+// (x1+x2)/2)); along non-grid dimensions the two segments share dv/2.
+template <typename R, int D>
+__device__ __forceinline__ void zigzag(R *sJ, const CurBox<D> &cb, const int32_t T[3], const R x1[3], const R x2[3],
+                                       const R dv[3], R q)
+{
+    R F1[3], F2[3], W1[3] = {0, 0, 0}, W2[3] = {0, 0, 0}, d1[3], d2[3];
+    int l1[3] = {0, 0, 0}, l2[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (d < D) {
+            R a = x1[d], b = x2[d];
+            R fa = floor(a), fb = floor(b);
+            R lo = fmin(fa, fb), hi = fmax(fa, fb);
+            R xr = fmin(lo + R(1), fmax(hi, R(0.5) * (a + b)));
+            d1[d] = xr - a;
+            d2[d] = b - xr;
+            F1[d] = q * d1[d];
+            F2[d] = q * d2[d];
+            W1[d] = R(0.5) * (a + xr) - fa;
+            W2[d] = R(0.5) * (b + xr) - fb;
+            l1[d] = (int)fa + T[d] / 2 + 1;
+            l2[d] = (int)fb + T[d] / 2 + 1;
+        } else {
+            R h = R(0.5) * dv[d];
+            d1[d] = h;
+            d2[d] = h;
+            F1[d] = q * h;
+            F2[d] = q * h;
+        }
+    }
+    deposit_segment<R, D>(sJ, cb, F1, W1, d1, l1);
+    deposit_segment<R, D>(sJ, cb, F2, W2, d2, l2);
+}
+
+// Tile offset code sum (delta_d+1) 3^d of a position after the push.
+template <typename R, int D>
+__device__ __forceinline__ int direction_code(const R x[3], const int32_t T[3], int delta[3])
+{
+    int code = 0, p3 = 1;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        R half = R(T[d] / 2);
+        delta[d] = x[d] < -half ? -1 : (x[d] >= half ? 1 : 0);
+        code += (delta[d] + 1) * p3;
+        p3 *= 3;
+    }
+    return code;
+}
+
+template <int D>
+__host__ __device__ constexpr int centre_code()
+{
+    return D == 1 ? 1 : (D == 2 ? 4 : 13);
+}
+
+template <int D>
+__host__ __device__ constexpr int ncodes()
+{
+    return D == 1 ? 3 : (D == 2 ? 9 : 27);
+}
+
+}  // namespace pic

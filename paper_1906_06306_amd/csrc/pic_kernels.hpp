@@ -1,0 +1,541 @@
+// Kernels of the relativistic PIC step for gfx950 (templated on precision
+// R and dimension D).  One work-group owns one tile: it stages the tile's
+// E and B (plus halo) in LDS, streams the tile's particles with coalesced
+// structure-of-arrays loads, accumulates the ZigZag current in an LDS block
+// with atomics and flushes that block once.  Field kernels also walk tiles.
+#pragma once
+
+#include "pic_device.hpp"
+
+namespace pic {
+
+constexpr int MAX_WAVES = 16;
+
+// Exclusive prefix of a per-thread flag over the whole work-group (wave
+// ballots, then per-wave totals in LDS).  sTot holds 2*MAX_WAVES ints and the
+// two halves alternate by `parity`, so one barrier per call suffices.
+__device__ __forceinline__ int wg_scan_flag(bool flag, int *sTot, int parity, int &total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    unsigned long long m = __ballot(flag);
+    int below = lanes_below(m);
+    int *tot = sTot + parity * MAX_WAVES;
+    if (lane == 0) tot[wave] = __popcll(m);
+    __syncthreads();
+    int off = 0, all = 0;
+    for (int w = 0; w < nw; ++w) {
+        int v = tot[w];
+        off += w < wave ? v : 0;
+        all += v;
+    }
+    total = all;
+    return off + below;
+}
+
+template <typename R, int D>
+__device__ __forceinline__ bool inside_tile(const R x[3], const int32_t T[3])
+{
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        R half = R(T[d] / 2);
+        ok = ok && (x[d] >= -half) && (x[d] < half);   // false for NaN
+    }
+    return ok;
+}
+
+// A pushed particle may be deposited when each displacement is below one
+// cell and the new position lies in the tile's current halo, so that the
+// ZigZag stencil stays inside the LDS block (rounding of x + dx could
+// otherwise reach the far face of the halo).
+template <typename R, int D>
+__device__ __forceinline__ bool moved_ok(const R x2[3], const R dv[3], const int32_t T[3])
+{
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        R lim = R(T[d] / 2 + 1);
+        ok = ok && fabs(dv[d]) < R(1) && x2[d] >= -lim && x2[d] < lim;
+    }
+    return ok;
+}
+
+template <typename R>
+__device__ __forceinline__ bool finite3(const R v[3])
+{
+    return isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]);
+}
+
+// Write one chunk of particles after the push: stayers compacted in place
+// (stable), leavers appended to the tile outbox rebased by -delta T.
+// Must be called by every thread of the work-group.
+template <typename R, int D>
+__device__ __forceinline__ void compact_chunk(const Params<R> &p, int ts, int64_t so, bool valid, int code,
+                                              const int delta[3], const R x2[3], const R u[3], int nvalid,
+                                              int *sTot, int &parity, int &keep, int &nleave)
+{
+    const bool stay = valid && code == centre_code<D>();
+    int tot;
+    int pre = wg_scan_flag(stay, sTot, parity, tot);
+    parity ^= 1;
+    const int64_t cap = p.cap_total;
+    if (stay) {
+        int64_t dst = so + keep + pre;
+#pragma unroll
+        for (int d = 0; d < D; ++d) p.pos[d * cap + dst] = x2[d];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) p.u[m * cap + dst] = u[m];
+    } else if (valid) {
+        int64_t slot = nleave + (threadIdx.x - pre);
+        if (slot < p.ob_cap) {
+            const int64_t ob = (int64_t)ts * p.ob_cap;
+#pragma unroll
+            for (int d = 0; d < D; ++d)
+                p.ob_pos[(ob * D) + d * p.ob_cap + slot] = x2[d] - R(delta[d] * p.T[d]);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) p.ob_u[(ob * 3) + m * p.ob_cap + slot] = u[m];
+            p.ob_dir[ob + slot] = code;
+        } else {
+            latch(p.err, ERR_CAPACITY);
+        }
+    }
+    keep += tot;
+    nleave += nvalid - tot;
+}
+
+// ------------------------------------------------------------------ push
+
+// interp_em + push (+ comp_curr and particle pack when FUSED) for one tile.
+template <typename R, int D, bool FUSED>
+__global__ void __launch_bounds__(1024) k_push(Params<R> p)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int t = p.order ? p.order[blockIdx.x] : (int)blockIdx.x;
+    const TileDesc td = p.tiles[t];
+    const FieldBox<D> fb(p.T);
+    const CurBox<D> cb(p.T);
+    R *sF = reinterpret_cast<R *>(smem);
+    R *sJ = sF + 6 * fb.n;
+    int *sTot = reinterpret_cast<int *>(sJ + (FUSED ? 3 * cb.n : 0));
+    stage_fields<R, D>(p, td, sF, fb);
+    if constexpr (FUSED) {
+        for (int k = threadIdx.x; k < 3 * cb.n; k += blockDim.x) sJ[k] = R(0);
+    }
+    __syncthreads();
+    const R c = p.c;
+    const int64_t cap = p.cap_total;
+    int parity = 0;
+    for (int s = 0; s < p.nspecies; ++s) {
+        const int ts = t * p.nspecies + s;
+        const int64_t so = p.seg_off[ts];
+        const int cnt = p.seg_cnt[ts];
+        const R q = p.charge[td.box * p.nspecies + s];
+        const R sq = p.qm[td.box * p.nspecies + s];
+        int keep = 0, nleave = 0;
+        for (int c0 = 0; c0 < cnt; c0 += blockDim.x) {
+            const int i = c0 + threadIdx.x;
+            bool valid = i < cnt;
+            R x[3] = {0, 0, 0}, u[3] = {0, 0, 0}, x2[3] = {0, 0, 0}, dv[3] = {0, 0, 0};
+            int delta[3] = {0, 0, 0};
+            int code = centre_code<D>();
+            if (valid) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) x[d] = p.pos[d * cap + so + i];
+#pragma unroll
+                for (int m = 0; m < 3; ++m) u[m] = p.u[m * cap + so + i];
+                if (inside_tile<R, D>(x, p.T)) {
+                    R e[3], b[3];
+                    interp_all<R, D>(sF, fb, x, p.T, e, b);
+                    boris<R>(u, e, b, c, sq);
+                    displacement<R>(u, c, dv);
+                    bool ok = finite3<R>(u);
+#pragma unroll
+                    for (int d = 0; d < D; ++d) x2[d] = x[d] + dv[d];
+                    ok = ok && moved_ok<R, D>(x2, dv, p.T);
+                    if (ok) {
+                        if constexpr (FUSED) {
+                            zigzag<R, D>(sJ, cb, p.T, x, x2, dv, q);
+                            code = direction_code<R, D>(x2, p.T, delta);
+                        }
+                    } else {
+                        latch(p.err, finite3<R>(u) ? ERR_CFL : ERR_NONFINITE);
+#pragma unroll
+                        for (int d = 0; d < D; ++d) x2[d] = x[d];
+                    }
+                } else {
+                    latch(p.err, ERR_OUT_OF_TILE);
+#pragma unroll
+                    for (int d = 0; d < D; ++d) x2[d] = x[d];
+                }
+            }
+            if constexpr (FUSED) {
+                const int nvalid = min((int)blockDim.x, cnt - c0);
+                compact_chunk<R, D>(p, ts, so, valid, code, delta, x2, u, nvalid, sTot, parity, keep, nleave);
+            } else if (valid) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    p.xold[d * cap + so + i] = x[d];
+                    p.pos[d * cap + so + i] = x2[d];
+                }
+#pragma unroll
+                for (int m = 0; m < 3; ++m) p.u[m * cap + so + i] = u[m];
+            }
+        }
+        if constexpr (FUSED) {
+            if (threadIdx.x == 0) {
+                p.seg_cnt[ts] = keep;
+                p.ob_cnt[ts] = nleave;
+            }
+        }
+    }
+    if constexpr (FUSED) {
+        __syncthreads();
+        R *blk = p.jblk + (int64_t)t * 3 * cb.n;
+        for (int k = threadIdx.x; k < 3 * cb.n; k += blockDim.x) blk[k] = sJ[k];
+    }
+}
+
+// comp_curr after an unfused push: ZigZag from (xold, pos) of every
+// particle into the tile's current block.
+template <typename R, int D>
+__global__ void __launch_bounds__(1024) k_deposit(Params<R> p)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int t = p.order ? p.order[blockIdx.x] : (int)blockIdx.x;
+    const TileDesc td = p.tiles[t];
+    const CurBox<D> cb(p.T);
+    R *sJ = reinterpret_cast<R *>(smem);
+    for (int k = threadIdx.x; k < 3 * cb.n; k += blockDim.x) sJ[k] = R(0);
+    __syncthreads();
+    const int64_t cap = p.cap_total;
+    for (int s = 0; s < p.nspecies; ++s) {
+        const int ts = t * p.nspecies + s;
+        const int64_t so = p.seg_off[ts];
+        const int cnt = p.seg_cnt[ts];
+        const R q = p.charge[td.box * p.nspecies + s];
+        for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+            R x1[3] = {0, 0, 0}, x2[3] = {0, 0, 0}, u[3], dv[3];
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                x1[d] = p.xold[d * cap + so + i];
+                x2[d] = p.pos[d * cap + so + i];
+            }
+#pragma unroll
+            for (int m = 0; m < 3; ++m) u[m] = p.u[m * cap + so + i];
+            displacement<R>(u, p.c, dv);
+            const bool ok = inside_tile<R, D>(x1, p.T) && finite3<R>(u) && moved_ok<R, D>(x2, dv, p.T);
+            if (ok) zigzag<R, D>(sJ, cb, p.T, x1, x2, dv, q);
+        }
+    }
+    __syncthreads();
+    R *blk = p.jblk + (int64_t)t * 3 * cb.n;
+    for (int k = threadIdx.x; k < 3 * cb.n; k += blockDim.x) blk[k] = sJ[k];
+}
+
+// cur_exchange: J on the lattice = sum of the current blocks of the tile
+// and of its neighbours whose halo covers the cell (fixed order).
+template <typename R, int D>
+__global__ void __launch_bounds__(256) k_fold(Params<R> p)
+{
+    const int t = blockIdx.x;
+    const TileDesc td = p.tiles[t];
+    const CurBox<D> cb(p.T);
+    const int T0 = p.T[0], T1 = D > 1 ? p.T[1] : 1, T2 = D > 2 ? p.T[2] : 1;
+    const int ncell = T0 * T1 * T2;
+    for (int k = threadIdx.x; k < ncell; k += blockDim.x) {
+        const int l[3] = {k % T0, (k / T0) % T1, k / (T0 * T1)};
+        R acc[3] = {0, 0, 0};
+        for (int oz = (D > 2 ? -1 : 0); oz <= (D > 2 ? 1 : 0); ++oz)
+            for (int oy = (D > 1 ? -1 : 0); oy <= (D > 1 ? 1 : 0); ++oy)
+                for (int ox = -1; ox <= 1; ++ox) {
+                    const int o[3] = {ox, oy, oz};
+                    int bi[3] = {0, 0, 0}, nc[3] = {0, 0, 0};
+                    bool in = true;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        if (d < D) {
+                            bi[d] = l[d] - o[d] * p.T[d] + 1;
+                            in = in && bi[d] >= 0 && bi[d] < p.T[d] + 3;
+                            nc[d] = wrapi(td.tc[d] + o[d], td.nt[d]);
+                        }
+                    }
+                    if (!in) continue;
+                    const int nid = td.tile0 + nc[0] + td.nt[0] * (nc[1] + td.nt[1] * nc[2]);
+                    const R *blk = p.jblk + (int64_t)nid * 3 * cb.n;
+                    const int idx = bi[0] + cb.e0 * (bi[1] + cb.e1 * bi[2]);
+                    acc[0] += blk[idx];
+                    acc[1] += blk[cb.n + idx];
+                    acc[2] += blk[2 * cb.n + idx];
+                }
+        const int gx = td.tc[0] * T0 + l[0];
+        const int gy = D > 1 ? td.tc[1] * T1 + l[1] : 0;
+        const int gz = D > 2 ? td.tc[2] * T2 + l[2] : 0;
+        const int64_t g = td.cell0 + gx + (int64_t)td.n[0] * (gy + (int64_t)td.n[1] * gz);
+        p.J[g] = acc[0];
+        p.J[p.cells_total + g] = acc[1];
+        p.J[2 * p.cells_total + g] = acc[2];
+    }
+}
+
+// ---------------------------------------------------------------- fields
+
+// PHASE 0: B -= h curl+ E.  PHASE 1: E += h curl- B.  PHASE 2: E -= J.
+// PHASE 3: E += h curl- B - J.   (Eqs. fdB/fdE, differences of App. B)
+template <typename R, int D, int PHASE>
+__global__ void __launch_bounds__(256) k_field(Params<R> p, R h)
+{
+    const int t = blockIdx.x;
+    const TileDesc td = p.tiles[t];
+    const int T0 = p.T[0], T1 = D > 1 ? p.T[1] : 1, T2 = D > 2 ? p.T[2] : 1;
+    const int ncell = T0 * T1 * T2;
+    const int64_t N = p.cells_total;
+    const int n0 = td.n[0], n1 = td.n[1], n2 = td.n[2];
+    for (int k = threadIdx.x; k < ncell; k += blockDim.x) {
+        const int gx = td.tc[0] * T0 + k % T0;
+        const int gy = D > 1 ? td.tc[1] * T1 + (k / T0) % T1 : 0;
+        const int gz = D > 2 ? td.tc[2] * T2 + k / (T0 * T1) : 0;
+        auto at = [&](int x, int y, int z) -> int64_t {
+            return td.cell0 + x + (int64_t)n0 * (y + (int64_t)n1 * z);
+        };
+        const int64_t g = at(gx, gy, gz);
+        if constexpr (PHASE == 0) {
+            const R *Ex = p.E, *Ey = p.E + N, *Ez = p.E + 2 * N;
+            const int64_t ip = D > 0 ? at(gx + 1 == n0 ? 0 : gx + 1, gy, gz) : g;
+            const int64_t jp = D > 1 ? at(gx, gy + 1 == n1 ? 0 : gy + 1, gz) : g;
+            const int64_t kp = D > 2 ? at(gx, gy, gz + 1 == n2 ? 0 : gz + 1) : g;
+            const R ex = Ex[g], ey = Ey[g], ez = Ez[g];
+            const R cx = (Ez[jp] - ez) - (Ey[kp] - ey);
+            const R cy = (Ex[kp] - ex) - (Ez[ip] - ez);
+            const R cz = (Ey[ip] - ey) - (Ex[jp] - ex);
+            p.B[g] -= h * cx;
+            p.B[N + g] -= h * cy;
+            p.B[2 * N + g] -= h * cz;
+        } else if constexpr (PHASE == 2) {
+            p.E[g] -= p.J[g];
+            p.E[N + g] -= p.J[N + g];
+            p.E[2 * N + g] -= p.J[2 * N + g];
+        } else {
+            const R *Bx = p.B, *By = p.B + N, *Bz = p.B + 2 * N;
+            const int64_t im = D > 0 ? at(gx == 0 ? n0 - 1 : gx - 1, gy, gz) : g;
+            const int64_t jm = D > 1 ? at(gx, gy == 0 ? n1 - 1 : gy - 1, gz) : g;
+            const int64_t km = D > 2 ? at(gx, gy, gz == 0 ? n2 - 1 : gz - 1) : g;
+            const R bx = Bx[g], by = By[g], bz = Bz[g];
+            const R cx = (bz - Bz[jm]) - (by - By[km]);
+            const R cy = (bx - Bx[km]) - (bz - Bz[im]);
+            const R cz = (by - By[im]) - (bx - Bx[jm]);
+            R ex = p.E[g] + h * cx, ey = p.E[N + g] + h * cy, ez = p.E[2 * N + g] + h * cz;
+            if constexpr (PHASE == 3) {
+                ex -= p.J[g];
+                ey -= p.J[N + g];
+                ez -= p.J[2 * N + g];
+            }
+            p.E[g] = ex;
+            p.E[N + g] = ey;
+            p.E[2 * N + g] = ez;
+        }
+    }
+}
+
+// ------------------------------------------------------------ migration
+
+// Tag and pack outflowing particles after an unfused push (stable).
+template <typename R, int D>
+__global__ void __launch_bounds__(1024) k_migrate_out(Params<R> p)
+{
+    __shared__ int sTot[2 * MAX_WAVES];
+    const int t = blockIdx.x;
+    const int64_t cap = p.cap_total;
+    int parity = 0;
+    for (int s = 0; s < p.nspecies; ++s) {
+        const int ts = t * p.nspecies + s;
+        const int64_t so = p.seg_off[ts];
+        const int cnt = p.seg_cnt[ts];
+        int keep = 0, nleave = 0;
+        for (int c0 = 0; c0 < cnt; c0 += blockDim.x) {
+            const int i = c0 + threadIdx.x;
+            const bool valid = i < cnt;
+            R x2[3] = {0, 0, 0}, u[3] = {0, 0, 0};
+            int delta[3] = {0, 0, 0}, code = centre_code<D>();
+            if (valid) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) x2[d] = p.pos[d * cap + so + i];
+#pragma unroll
+                for (int m = 0; m < 3; ++m) u[m] = p.u[m * cap + so + i];
+                code = direction_code<R, D>(x2, p.T, delta);
+            }
+            const int nvalid = min((int)blockDim.x, cnt - c0);
+            compact_chunk<R, D>(p, ts, so, valid, code, delta, x2, u, nvalid, sTot, parity, keep, nleave);
+        }
+        if (threadIdx.x == 0) {
+            p.seg_cnt[ts] = keep;
+            p.ob_cnt[ts] = nleave;
+        }
+    }
+}
+
+// Receive incoming particles: append, per direction code in increasing
+// order, the neighbour outbox entries addressed to this tile.
+template <typename R, int D>
+__global__ void __launch_bounds__(1024) k_migrate_in(Params<R> p)
+{
+    __shared__ int sTot[2 * MAX_WAVES];
+    const int t = blockIdx.x;
+    const TileDesc td = p.tiles[t];
+    const int64_t cap = p.cap_total;
+    int parity = 0;
+    for (int s = 0; s < p.nspecies; ++s) {
+        const int ts = t * p.nspecies + s;
+        const int64_t so = p.seg_off[ts];
+        const int scap = p.seg_cap[ts];
+        int cnt = p.seg_cnt[ts];
+        for (int code = 0; code < ncodes<D>(); ++code) {
+            if (code == centre_code<D>()) continue;
+            int nc[3] = {0, 0, 0}, rem = code;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                if (d < D) {
+                    int delta = rem % 3 - 1;
+                    rem /= 3;
+                    nc[d] = wrapi(td.tc[d] - delta, td.nt[d]);
+                }
+            }
+            const int sid = td.tile0 + nc[0] + td.nt[0] * (nc[1] + td.nt[1] * nc[2]);
+            const int sts = sid * p.nspecies + s;
+            const int m = (int)min((int64_t)p.ob_cnt[sts], p.ob_cap);
+            const int64_t ob = (int64_t)sts * p.ob_cap;
+            for (int c0 = 0; c0 < m; c0 += blockDim.x) {
+                const int k = c0 + threadIdx.x;
+                const bool take = k < m && p.ob_dir[ob + k] == code;
+                int tot;
+                int pre = wg_scan_flag(take, sTot, parity, tot);
+                parity ^= 1;
+                if (take) {
+                    const int dst = cnt + pre;
+                    if (dst < scap) {
+#pragma unroll
+                        for (int d = 0; d < D; ++d) p.pos[d * cap + so + dst] = p.ob_pos[ob * D + d * p.ob_cap + k];
+#pragma unroll
+                        for (int mm = 0; mm < 3; ++mm) p.u[mm * cap + so + dst] = p.ob_u[ob * 3 + mm * p.ob_cap + k];
+                    } else {
+                        latch(p.err, ERR_CAPACITY);
+                    }
+                }
+                cnt += tot;
+            }
+        }
+        if (threadIdx.x == 0) p.seg_cnt[ts] = min(cnt, scap);
+    }
+}
+
+// Stable sort of every tile segment by cell index (x fastest).  Each wave
+// takes a contiguous quarter (or 1/nwaves) of the segment; per-wave cell
+// histograms are scanned in (cell, wave) order, then each wave scatters its
+// range in order, ranking equal keys among lanes with ballots.  Output goes
+// to the staging arrays and is copied back.
+template <typename R, int D>
+__global__ void __launch_bounds__(256) k_cell_sort(Params<R> p)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int t = blockIdx.x;
+    const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int T0 = p.T[0], T1 = D > 1 ? p.T[1] : 1, T2 = D > 2 ? p.T[2] : 1;
+    const int ncell = T0 * T1 * T2;
+    int *hist = reinterpret_cast<int *>(smem);      // [nw][ncell]
+    __shared__ unsigned long long nf_block;
+    int nbits = 0;
+    while ((1 << nbits) < ncell) ++nbits;
+    const int64_t cap = p.cap_total;
+    if (threadIdx.x == 0) nf_block = 0;
+    for (int s = 0; s < p.nspecies; ++s) {
+        const int ts = t * p.nspecies + s;
+        const int64_t so = p.seg_off[ts];
+        const int cnt = p.seg_cnt[ts];
+        const int per = (cnt + nw - 1) / nw;
+        const int lo = min(cnt, wave * per), hi = min(cnt, lo + per);
+        for (int k = threadIdx.x; k < nw * ncell; k += blockDim.x) hist[k] = 0;
+        __syncthreads();
+        auto keyof = [&](int64_t idx) -> int {
+            int key = 0, stride = 1;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                R v = p.pos[d * cap + idx];
+                int c = (int)floor(v) + p.T[d] / 2;
+                c = min(max(c, 0), p.T[d] - 1);
+                key += c * stride;
+                stride *= p.T[d];
+            }
+            return key;
+        };
+        for (int i = lo + lane; i < hi; i += 64) atomicAdd(&hist[wave * ncell + keyof(so + i)], 1);
+        __syncthreads();
+        // exclusive scan over (cell, wave): one thread per cell, serial over
+        // waves, then a block scan of the per-cell totals
+        int *tot = hist + nw * ncell;   // [ncell] scratch for cell totals
+        for (int k = threadIdx.x; k < ncell; k += blockDim.x) {
+            int run = 0;
+            for (int w = 0; w < nw; ++w) {
+                int v = hist[w * ncell + k];
+                hist[w * ncell + k] = run;
+                run += v;
+            }
+            tot[k] = run;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int run = 0;
+            for (int k = 0; k < ncell; ++k) {
+                int v = tot[k];
+                tot[k] = run;
+                run += v;
+            }
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < nw * ncell; k += blockDim.x) hist[k] += tot[k % ncell];
+        __syncthreads();
+        // in-order scatter, 64 particles at a time per wave
+        for (int base = lo; base < hi; base += 64) {
+            const int i = base + lane;
+            const bool valid = i < hi;
+            const int key = valid ? keyof(so + i) : 0;
+            unsigned long long m = __ballot(valid);
+            for (int b = 0; b < nbits; ++b) {
+                unsigned long long bb = __ballot((key >> b) & 1);
+                m &= ((key >> b) & 1) ? bb : ~bb;
+            }
+            int old = 0;
+            if (valid) old = hist[wave * ncell + key];
+            const int rank = lanes_below(m);
+            const int lead = __ffsll((long long)m) - 1;
+            if (valid && lane == lead) hist[wave * ncell + key] = old + __popcll(m);
+            if (valid) {
+                const int64_t dst = so + old + rank;
+#pragma unroll
+                for (int d = 0; d < D; ++d) p.tmp[d * cap + dst] = p.pos[d * cap + so + i];
+#pragma unroll
+                for (int mm = 0; mm < 3; ++mm) p.tmp[(D + mm) * cap + dst] = p.u[mm * cap + so + i];
+            }
+        }
+        __threadfence_block();
+        __syncthreads();
+        unsigned long long nf = 0;
+        for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+            bool flag = false;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                R v = p.tmp[d * cap + so + i];
+                p.pos[d * cap + so + i] = v;
+                R av = fabs(v);
+                R ulp = nextafter(av, R(INFINITY)) - av;
+                flag = flag || fabs(v - rint(v)) <= ulp;
+            }
+#pragma unroll
+            for (int mm = 0; mm < 3; ++mm) p.u[mm * cap + so + i] = p.tmp[(D + mm) * cap + so + i];
+            nf += flag;
+        }
+        if (nf) atomicAdd(&nf_block, nf);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && nf_block) atomicAdd(p.nearface, nf_block);
+}
+
+}  // namespace pic

@@ -1,0 +1,224 @@
+"""Thin Python driver over libpic: PyTorch owns the device workspace and the
+stream; every step of the method runs in the library's HIP kernels."""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+@dataclass
+class Box:
+    """One periodic box: FP64 global state in code units (App. A)."""
+    D: int
+    n: tuple                 # (n0, n1, n2)
+    c: float
+    charge: list             # per species q
+    qm: list                 # per species s = q/(m m_pm)
+    mass: list               # per species macro-particle mass
+    pos: list                # per species (D, np) FP64 global positions
+    u: list                  # per species (3, np) FP64 four-velocities
+    E: np.ndarray            # (3, N)
+    B: np.ndarray            # (3, N)
+
+
+def box_from_plasma(p) -> Box:
+    """Adapter for objects with the attributes of synth.Plasma."""
+    return Box(D=p.D, n=tuple(p.n), c=p.c, charge=[s.q for s in p.species], qm=[s.s for s in p.species],
+               mass=[s.m for s in p.species], pos=[s.x for s in p.species], u=[s.u for s in p.species],
+               E=p.E, B=p.B)
+
+
+class PicSim:
+    """A batch of periodic boxes stepped together on one GPU."""
+
+    def __init__(self, boxes, tile, precision: str = "fp32", block: int = 256, capacity_factor: float = 1.25,
+                 tile_capacity=None, outbox_capacity: int = 0, device: str = "cuda:0"):
+        if not isinstance(boxes, (list, tuple)):
+            boxes = [boxes]
+        boxes = [b if isinstance(b, Box) else box_from_plasma(b) for b in boxes]
+        self.boxes = boxes
+        b0 = boxes[0]
+        self.D = b0.D
+        self.ns = len(b0.charge)
+        self.nb = len(boxes)
+        self.c = float(b0.c)
+        for b in boxes:
+            if b.D != self.D or len(b.charge) != self.ns or float(b.c) != self.c:
+                raise ValueError("all boxes must share D, species count and Courant number")
+        self.T = tuple(int(t) for t in tile) + (1,) * (3 - len(tile))
+        self.prec = L.PIC_FP64 if precision == "fp64" else L.PIC_FP32
+        self.dtype = torch.float64 if self.prec == L.PIC_FP64 else torch.float32
+        self.device = torch.device(device)
+        lib = L.lib()
+        # host arrays referenced by the config (kept alive on self)
+        self._cells = np.array([list(b.n) + [1] * (3 - len(b.n)) for b in boxes], dtype=np.int32)
+        self._charge = np.array([b.charge for b in boxes], dtype=np.float64)
+        self._qm = np.array([b.qm for b in boxes], dtype=np.float64)
+        self._mass = np.array([b.mass for b in boxes], dtype=np.float64)
+        self._counts = np.array([[p.shape[1] for p in b.pos] for b in boxes], dtype=np.int64)
+        self._tcap = None if tile_capacity is None else np.ascontiguousarray(tile_capacity, dtype=np.int64)
+        cfg = L.PicConfig()
+        cfg.dim = self.D
+        cfg.precision = self.prec
+        cfg.n_species = self.ns
+        cfg.n_boxes = self.nb
+        for d in range(3):
+            cfg.tile[d] = self.T[d]
+        cfg.block = block
+        cfg.cfl = self.c
+        cfg.box_cells = self._cells.ctypes.data
+        cfg.charge = self._charge.ctypes.data
+        cfg.qm = self._qm.ctypes.data
+        cfg.mass = self._mass.ctypes.data
+        cfg.tile_capacity = None if self._tcap is None else self._tcap.ctypes.data
+        cfg.capacity_factor = capacity_factor
+        cfg.outbox_capacity = outbox_capacity
+        self.cfg = cfg
+        lay = L.PicLayout()
+        L.check(lib.pic_query(ctypes.byref(cfg), self._counts.ctypes.data, ctypes.byref(lay)))
+        self.layout = lay
+        self.ws = torch.empty(int(lay.total_bytes) + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        self._shift = (-base) % 256
+        self.ws_ptr = base + self._shift
+        # initial FP64 state, uploaded for the binning kernels
+        keep = []
+        pos_ptrs, u_ptrs, e_ptrs, b_ptrs = [], [], [], []
+        for b in boxes:
+            for s in range(self.ns):
+                pt = torch.as_tensor(np.ascontiguousarray(b.pos[s], dtype=np.float64)).to(self.device)
+                ut = torch.as_tensor(np.ascontiguousarray(b.u[s], dtype=np.float64)).to(self.device)
+                keep += [pt, ut]
+                pos_ptrs.append(pt.data_ptr())
+                u_ptrs.append(ut.data_ptr())
+            et = torch.as_tensor(np.ascontiguousarray(b.E, dtype=np.float64)).to(self.device)
+            bt = torch.as_tensor(np.ascontiguousarray(b.B, dtype=np.float64)).to(self.device)
+            keep += [et, bt]
+            e_ptrs.append(et.data_ptr())
+            b_ptrs.append(bt.data_ptr())
+        n_src = self.nb * self.ns
+        self._pos_arr = (ctypes.c_void_p * n_src)(*pos_ptrs)
+        self._u_arr = (ctypes.c_void_p * n_src)(*u_ptrs)
+        self._e_arr = (ctypes.c_void_p * self.nb)(*e_ptrs)
+        self._b_arr = (ctypes.c_void_p * self.nb)(*b_ptrs)
+        init = L.PicInitData(self._counts.ctypes.data, ctypes.cast(self._pos_arr, ctypes.c_void_p),
+                             ctypes.cast(self._u_arr, ctypes.c_void_p), ctypes.cast(self._e_arr, ctypes.c_void_p),
+                             ctypes.cast(self._b_arr, ctypes.c_void_p))
+        self.stream = torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        L.check(lib.pic_init_tiles(ctypes.byref(cfg), self._counts.ctypes.data, ctypes.c_void_p(self.ws_ptr),
+                                   int(lay.total_bytes), ctypes.byref(init), ctypes.c_void_p(self.stream.cuda_stream),
+                                   ctypes.byref(ctx)))
+        self.ctx = ctx
+        del keep
+        # box geometry on the host for readback
+        self.nt = [[b.n[d] // self.T[d] if d < self.D else 1 for d in range(3)] for b in boxes]
+        self.tile0 = np.cumsum([0] + [int(np.prod(nt)) for nt in self.nt])[:-1]
+        self.cell0 = np.cumsum([0] + [int(np.prod(c)) for c in self._cells])[:-1]
+
+    # ------------------------------------------------------------ calls
+    def fdtd(self, phase: int):
+        L.check(L.lib().pic_fdtd_step(self.ctx, phase))
+
+    def push(self, fused: bool = True):
+        L.check(L.lib().pic_push_interp(self.ctx, L.PIC_FUSED if fused else 0))
+
+    def deposit(self):
+        L.check(L.lib().pic_deposit_current(self.ctx, 0))
+
+    def sort_migrate(self, sort_cells: bool = False):
+        L.check(L.lib().pic_sort_migrate(self.ctx, L.PIC_SORT_CELLS if sort_cells else 0))
+
+    def step(self, n: int = 1, fused: bool = True, sort_cells: bool = False):
+        flags = (L.PIC_FUSED if fused else 0) | (L.PIC_SORT_CELLS if sort_cells else 0)
+        fn = L.lib().pic_step
+        for _ in range(n):
+            L.check(fn(self.ctx, flags))
+
+    def error(self) -> int:
+        code = L.lib().pic_error(self.ctx)
+        return code
+
+    def diagnostics(self) -> dict:
+        d = L.PicDiag()
+        code = L.lib().pic_diagnostics(self.ctx, ctypes.byref(d))
+        if code not in (0,) and code < (1 << 8):
+            L.check(code)
+        return dict(field_energy=d.field_energy, kinetic_energy=d.kinetic_energy, gauss_max=d.gauss_max,
+                    divb_max=d.divb_max, charge_total=d.charge_total, particles=d.particles,
+                    near_face=d.near_face, error_bits=d.error_bits, status=code)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            L.lib().pic_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ----------------------------------------------------------- views
+    def _view(self, off: int, count: int, dtype) -> torch.Tensor:
+        esize = torch.empty((), dtype=dtype).element_size()
+        start = self._shift + int(off)
+        return self.ws[start:start + count * esize].view(dtype)
+
+    def field_views(self):
+        N = int(self.layout.cells_total)
+        E = self._view(self.layout.off_E, 3 * N, self.dtype).view(3, N)
+        B = self._view(self.layout.off_B, 3 * N, self.dtype).view(3, N)
+        J = self._view(self.layout.off_J, 3 * N, self.dtype).view(3, N)
+        return E, B, J
+
+    def particle_views(self):
+        cap = int(self.layout.capacity_total)
+        pos = self._view(self.layout.off_pos, self.D * cap, self.dtype).view(self.D, cap)
+        u = self._view(self.layout.off_u, 3 * cap, self.dtype).view(3, cap)
+        xold = self._view(self.layout.off_xold, self.D * cap, self.dtype).view(self.D, cap)
+        nts = int(self.layout.tiles_total) * self.ns
+        off = self._view(self.layout.off_seg_offset, nts, torch.int64).view(-1, self.ns)
+        cnt = self._view(self.layout.off_seg_count, nts, torch.int32).view(-1, self.ns)
+        return pos, u, xold, off, cnt
+
+    def fields_host(self, box: int = 0):
+        """E, B, J of one box as FP64 numpy arrays (3, N)."""
+        torch.cuda.synchronize(self.device)
+        E, B, J = self.field_views()
+        a = int(self.cell0[box])
+        n = int(np.prod(self._cells[box]))
+        return tuple(t[:, a:a + n].double().cpu().numpy() for t in (E, B, J))
+
+    def particles_host(self, box: int = 0, species: int = 0, with_xold: bool = False):
+        """Particles of one box and species in storage order (tiles in id
+        order): (tile_id (np,), x_loc (D, np) in the working precision,
+        u (3, np)[, xold (D, np)])."""
+        torch.cuda.synchronize(self.device)
+        pos, u, xold, off, cnt = self.particle_views()
+        off = off.cpu().numpy()
+        cnt = cnt.cpu().numpy()
+        t0 = int(self.tile0[box])
+        ntb = int(np.prod(self.nt[box]))
+        idx, tid = [], []
+        for t in range(t0, t0 + ntb):
+            o, c = int(off[t, species]), int(cnt[t, species])
+            idx.append(np.arange(o, o + c))
+            tid.append(np.full(c, t - t0, dtype=np.int64))
+        idx = np.concatenate(idx) if idx else np.zeros(0, dtype=np.int64)
+        tid = np.concatenate(tid) if tid else np.zeros(0, dtype=np.int64)
+        it = torch.as_tensor(idx, device=self.device)
+        out = [tid, pos[:, it].cpu().numpy(), u[:, it].cpu().numpy()]
+        if with_xold:
+            out.append(xold[:, it].cpu().numpy())
+        return tuple(out)
+
+    def counts_host(self):
+        torch.cuda.synchronize(self.device)
+        _, _, _, _, cnt = self.particle_views()
+        return cnt.cpu().numpy()

@@ -1,0 +1,247 @@
+"""GPU-vs-oracle parity of every kernel of the step, through the C ABI.
+
+Each test starts the HIP path and the FP64 oracle from one common state: the
+GPU's own binned state (tile-local positions widened exactly to FP64 global
+coordinates where the precision allows, fields widened from the working
+precision).  Floating-point outputs must agree to relative L2 1e-12 (FP64
+path) or 1e-5 (FP32 path); integer work (tile binning, migration order and
+counts, cell sort) must be bit-exact.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import tiles
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def make_sim(plasma, T, prec, **kw):
+    from paper_1906_06306_amd.sim import PicSim
+    print(f"[gpu] PicSim D={plasma.D} n={plasma.n} T={T} prec={prec} np={plasma.nparticles}", flush=True)
+    return PicSim(plasma, tile=T, precision=prec, **kw)
+
+
+def common_state(sim, plasma):
+    """Oracle state equal to what the GPU holds (widened to FP64)."""
+    st = oracle.State(plasma)
+    E, B, J = sim.fields_host(0)
+    st.E[:] = E
+    st.B[:] = B
+    for s in range(len(plasma.species)):
+        tid, xl, u = sim.particles_host(0, s)
+        st.x[s] = np.ascontiguousarray(tiles.to_global(tid, xl, plasma.n, sim.T, plasma.D))
+        st.u[s] = np.ascontiguousarray(u.astype(np.float64))
+    return st
+
+
+CASES = [
+    # (D, n, T, ppc)
+    (1, (96, 1, 1), (16, 1, 1), 24),
+    (2, (48, 40, 1), (8, 8, 1), 6),
+    (3, (16, 16, 12), (8, 8, 4), 2),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("D,n,T,ppc", CASES)
+def test_init_binning_bit_exact(D, n, T, ppc, prec):
+    plasma = synth.small_random(D, n, ppc, seed=3 + D)
+    sim = make_sim(plasma, T, prec)
+    dt = np.float64 if prec == "fp64" else np.float32
+    for s, sp in enumerate(plasma.species):
+        tid, xl, order = tiles.bin_global(sp.x, n, T, D, dt)
+        g_tid, g_xl, g_u = sim.particles_host(0, s)
+        assert np.array_equal(g_tid, tid[order])
+        assert np.array_equal(g_xl, xl[:, order])
+        assert np.array_equal(g_u, sp.u[:, order].astype(dt))
+    E, B, J = sim.fields_host(0)
+    assert np.array_equal(E, plasma.E.astype(dt).astype(np.float64))
+    assert not J.any()
+    d = sim.diagnostics()
+    flags = sum(int(tiles.near_face(sim.particles_host(0, s)[1], D).sum()) for s in range(2))
+    assert d["near_face"] == flags
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("D,n,T,ppc", CASES)
+def test_unfused_step_stage_by_stage(D, n, T, ppc, prec):
+    """Table-1 order through the separate entry points; each stage is
+    compared with the oracle routine applied to the same inputs."""
+    from paper_1906_06306_amd import _lib as L
+    plasma = synth.small_random(D, n, ppc, seed=11 + D, field_amp=0.05)
+    sim = make_sim(plasma, T, prec)
+    st = common_state(sim, plasma)
+    tol = TOL[prec]
+    c = plasma.c
+    # push_half_b1
+    sim.fdtd(L.PIC_HALF_B)
+    oracle.advance_b(D, n, 0.5 * c, st.E, st.B)
+    E, B, _ = sim.fields_host(0)
+    assert rel(B, st.B) < tol
+    # interp_em + push (unfused: positions stay in their tile, unrebased)
+    sim.push(fused=False)
+    x_old = [x.copy() for x in st.x]
+    disp = []
+    for s in range(2):
+        Ep, Bp = oracle.interp(D, n, st.E, st.B, st.x[s])
+        oracle.boris(c, st.s[s], Ep, Bp, st.u[s])
+        disp.append(oracle.move(D, c, st.u[s], st.x[s]))
+        tid, xl, u, xo = sim.particles_host(0, s, with_xold=True)
+        gx = tiles.to_global(tid, xl, n, T, D)
+        assert rel(u.astype(np.float64), st.u[s]) < tol
+        assert np.abs(gx - st.x[s]).max() < (1e-12 if prec == "fp64" else 4e-6 * max(T))
+        assert np.array_equal(tiles.to_global(tid, xo, n, T, D), x_old[s])
+    # push_half_b2
+    sim.fdtd(L.PIC_HALF_B)
+    oracle.advance_b(D, n, 0.5 * c, st.E, st.B)
+    # comp_curr + halo fold
+    sim.deposit()
+    J = np.zeros_like(st.E)
+    for s in range(2):
+        oracle.zigzag(D, n, st.q[s], x_old[s], st.x[s], disp[s], J)
+    _, B, Jg = sim.fields_host(0)
+    assert rel(B, st.B) < tol
+    assert rel(Jg, J) < tol, rel(Jg, J)
+    # push_e + add_cur
+    sim.fdtd(L.PIC_CURL_E_ADD_J)
+    oracle.advance_e(D, n, c, st.B, st.E)
+    oracle.add_current(n, J, st.E)
+    E, _, _ = sim.fields_host(0)
+    assert rel(E, st.E) < tol
+    # particle communication: bit-exact against the rule applied to the
+    # GPU's own pushed positions
+    before = [sim.particles_host(0, s) for s in range(2)]
+    sim.sort_migrate()
+    for s in range(2):
+        tid, xl, u = before[s]
+        perm, ntid, nxl, counts = tiles.migrate(tid, xl, T, D, n)
+        g_tid, g_xl, g_u = sim.particles_host(0, s)
+        assert np.array_equal(g_tid, ntid)
+        assert np.array_equal(g_xl, nxl)
+        assert np.array_equal(g_u, u[:, perm])
+        assert np.array_equal(np.bincount(g_tid, minlength=counts.size), counts)
+    assert sim.error() == 0
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("D,n,T,ppc", CASES)
+def test_fused_step_matches_oracle_and_unfused(D, n, T, ppc, prec):
+    """One fused step (push + deposit + pack in one kernel) against the
+    oracle's full step, and its particle arrays against the unfused path."""
+    plasma = synth.small_random(D, n, ppc, seed=21 + D, field_amp=0.05)
+    sim = make_sim(plasma, T, prec)
+    ref = make_sim(plasma, T, prec)
+    st = common_state(sim, plasma)
+    sim.step(1, fused=True)
+    ref.step(1, fused=False)
+    st.step(1)
+    tol = TOL[prec]
+    E, B, J = sim.fields_host(0)
+    assert rel(B, st.B) < tol and rel(J, st.J) < tol and rel(E, st.E) < tol
+    # same arithmetic in two kernels: identical tiles and order, values to
+    # rounding (the compiler may contract multiply-adds differently)
+    ptol = 1e-13 if prec == "fp64" else 1e-6
+    for s in range(2):
+        a = sim.particles_host(0, s)
+        b = ref.particles_host(0, s)
+        assert np.array_equal(a[0], b[0])
+        assert np.abs(a[1] - b[1]).max() <= ptol * max(T)
+        assert rel(a[2].astype(np.float64), b[2].astype(np.float64)) < ptol
+    assert sim.error() == 0
+    sim.close()
+    ref.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_cell_sort_bit_exact(prec):
+    D, n, T = 2, (64, 32, 1), (16, 8, 1)
+    plasma = synth.small_random(D, n, 5, seed=5)
+    sim = make_sim(plasma, T, prec)
+    sim.step(1, fused=True)
+    before = [sim.particles_host(0, s) for s in range(2)]
+    sim.sort_migrate(sort_cells=True)
+    nf = 0
+    for s in range(2):
+        tid, xl, u = before[s]
+        perm = tiles.cell_sort(tid, xl, T, D)
+        g = sim.particles_host(0, s)
+        assert np.array_equal(g[0], tid[perm]) and np.array_equal(g[1], xl[:, perm])
+        assert np.array_equal(g[2], u[:, perm])
+        nf += int(tiles.near_face(g[1], D).sum())
+    assert sim.diagnostics()["near_face"] == nf
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_multistep_invariants(prec):
+    """Gauss's law and div B through 20 fused steps (diagnostics in FP64);
+    the FP32 path keeps them at FP32 round-off of the stored fields."""
+    plasma = synth.turbulence(n=64, ppc=4, seed=9)
+    sim = make_sim(plasma, (16, 16), prec)
+    d0 = sim.diagnostics()
+    sim.step(20, fused=True)
+    d = sim.diagnostics()
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    assert d["status"] == 0
+    assert d["gauss_max"] < tol and d["divb_max"] < tol * max(1.0, 10 * abs(plasma.meta["B0"]))
+    assert d["particles"] == d0["particles"] == plasma.nparticles
+    assert abs(d["charge_total"]) < 1e-9
+    sim.close()
+
+
+def test_multibox_matches_single_boxes():
+    """Two boxes of different sizes in one batch step exactly like each box
+    alone (FP64)."""
+    from paper_1906_06306_amd.sim import PicSim
+    a = synth.thermal_box(32, 48, 3, 0.2, seed=1)
+    b = synth.thermal_box(64, 16, 2, 0.05, seed=2)
+    for p in (a, b):
+        p.E[:] = 0.01 * np.random.default_rng(0).standard_normal(p.E.shape)
+    batch = PicSim([a, b], tile=(16, 16), precision="fp64")
+    one = [PicSim(p, tile=(16, 16), precision="fp64") for p in (a, b)]
+    batch.step(3)
+    for i, s1 in enumerate(one):
+        s1.step(3)
+        for x, y in zip(batch.fields_host(i), s1.fields_host(0)):
+            assert rel(x, y) < 1e-13
+        # LDS atomics add in no fixed order, so values agree to rounding
+        for s in range(2):
+            a, b_ = batch.particles_host(i, s), s1.particles_host(0, s)
+            assert np.array_equal(a[0], b_[0])
+            assert np.abs(a[1] - b_[1]).max() < 1e-12 and np.abs(a[2] - b_[2]).max() < 1e-12
+        s1.close()
+    batch.close()
+
+
+def test_capacity_overflow_is_reported():
+    """A segment too small for its particles latches PIC_E_CAPACITY at init
+    (forced from the host with a tiny capacity; no kernel goes out of
+    bounds)."""
+    from paper_1906_06306_amd import _lib as L
+    plasma = synth.small_random(2, (32, 32), 4, seed=1)
+    nt = 4 * 4
+    cap = np.full((nt, 2), 64, dtype=np.int64)
+    with pytest.raises(L.PicError) as e:
+        make_sim(plasma, (8, 8), "fp32", tile_capacity=cap)
+    assert e.value.code & L.PIC_E_CAPACITY
+
+
+def test_positions_outside_box_are_reported():
+    from paper_1906_06306_amd import _lib as L
+    plasma = synth.small_random(2, (32, 32), 2, seed=2)
+    plasma.species[0].x[0, 5] = 40.0
+    with pytest.raises(L.PicError) as e:
+        make_sim(plasma, (8, 8), "fp32")
+    assert e.value.code & L.PIC_E_OUT_OF_TILE
