@@ -47,6 +47,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many fused steps (for rocprofv3), no JSON")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"],
+                    help="precision of the --profile-steps run")
+    ap.add_argument("--capacity", type=float, default=2.0,
+                    help="tile segment capacity over the mean count (turbulent compression)")
     return ap.parse_args()
 
 
@@ -68,7 +72,8 @@ def run_gpu(plasma, args, precision, steps, warmup, profile_only=False):
     from paper_1906_06306_amd import _lib as L
     from paper_1906_06306_amd.sim import PicSim
 
-    sim = PicSim(plasma, tile=(args.tile, args.tile), precision=precision, block=args.block)
+    sim = PicSim(plasma, tile=(args.tile, args.tile), precision=precision, block=args.block,
+                 capacity_factor=args.capacity)
     stream = torch.cuda.current_stream()
     lib = L.lib()
     ctx = sim.ctx
@@ -134,7 +139,7 @@ def main():
     log(f"generated {plasma.nparticles} particles on {args.n}^2 cells in {time.perf_counter() - t0:.1f}s")
     n_p, n_c, D = plasma.nparticles, plasma.ncells, plasma.D
     if args.profile_steps:
-        code = run_gpu(plasma, args, "fp32", args.profile_steps, 0, profile_only=True)
+        code = run_gpu(plasma, args, args.precision, args.profile_steps, 0, profile_only=True)
         log(f"profile run done, device status {code}")
         return
     log("fp32 run")

@@ -108,8 +108,13 @@ typedef struct {
                                    rounded up to 64 (default 1.25 if <= 0)    */
     int32_t outbox_capacity;    /* leavers per (tile, species) per step; 0 =
                                    default (a quarter of the segment, >= 256) */
-    int32_t reserved;
+    uint32_t options;           /* PIC_OPT_* bits, 0 = defaults              */
 } pic_config;
+
+/* pic_config.options: accumulate the tile current block in LDS in the
+ * working precision instead of FP64 (the default; the block is rounded to
+ * the working precision once when it is written out). */
+#define PIC_OPT_ACC_WORKING 1u
 
 /* Byte offsets of the regions inside the caller's workspace.  Fields:
  * [3][cells_total] each, boxes concatenated (box b starts at cell offset

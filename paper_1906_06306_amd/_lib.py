@@ -24,6 +24,7 @@ PIC_ADD_J = 2
 PIC_CURL_E_ADD_J = 3
 PIC_FUSED = 1
 PIC_SORT_CELLS = 2
+PIC_OPT_ACC_WORKING = 1
 
 EXPORTS = ["pic_query", "pic_init_tiles", "pic_fdtd_step", "pic_push_interp", "pic_deposit_current",
            "pic_sort_migrate", "pic_step", "pic_error", "pic_diagnostics", "pic_destroy", "pic_last_error"]
@@ -41,7 +42,7 @@ class PicConfig(ctypes.Structure):
         ("dim", I32), ("precision", I32), ("n_species", I32), ("n_boxes", I32),
         ("tile", I32 * 3), ("block", I32), ("cfl", DBL),
         ("box_cells", P), ("charge", P), ("qm", P), ("mass", P), ("tile_capacity", P),
-        ("capacity_factor", DBL), ("outbox_capacity", I32), ("reserved", I32),
+        ("capacity_factor", DBL), ("outbox_capacity", I32), ("options", U32),
     ]
 
 

@@ -219,6 +219,7 @@ pic_status make_layout(const pic_config *c, const int64_t *counts, Layout &L)
 
 struct pic_ctx {
     int D, prec, ns, nb, block;
+    bool acc_working;   // LDS current block in the working precision
     int T[3];
     double c;
     Layout L;
@@ -290,14 +291,14 @@ pic_status fill(pic_ctx *x, T *p, int64_t n, T v)
 
 template <typename R, int D>
 struct Impl {
-    static size_t push_lds(pic_ctx *x, bool fused)
+    static size_t push_lds(pic_ctx *x, bool fused, size_t acc_bytes)
     {
         int64_t fbn = 1, cbn = 1;
         for (int d = 0; d < D; ++d) {
             fbn *= x->T[d] + 2;
             cbn *= x->T[d] + 3;
         }
-        return (6 * fbn + (fused ? 3 * cbn : 0)) * sizeof(R) + 2 * pic::MAX_WAVES * sizeof(int);
+        return 6 * fbn * sizeof(R) + (fused ? 3 * cbn * acc_bytes : 0) + 2 * pic::MAX_WAVES * sizeof(int);
     }
 
     static pic_status fdtd(pic_ctx *x, int phase)
@@ -316,22 +317,23 @@ struct Impl {
         return PIC_OK;
     }
 
-    static pic_status push(pic_ctx *x, bool fused)
+    template <bool FUSED, typename A>
+    static pic_status push_with(pic_ctx *x)
     {
         Params<R> p = params<R>(x);
-        size_t lds = push_lds(x, fused);
+        size_t lds = push_lds(x, FUSED, sizeof(A));
         dim3 g((unsigned)x->L.pub.tiles_total), b(x->block);
-        if (fused) {
-            pic_status st = set_lds(pic::k_push<R, D, true>, lds);
-            if (st) return st;
-            hipLaunchKernelGGL((pic::k_push<R, D, true>), g, b, lds, x->stream, p);
-        } else {
-            pic_status st = set_lds(pic::k_push<R, D, false>, lds);
-            if (st) return st;
-            hipLaunchKernelGGL((pic::k_push<R, D, false>), g, b, lds, x->stream, p);
-        }
+        pic_status st = set_lds(pic::k_push<R, D, FUSED, A>, lds);
+        if (st) return st;
+        hipLaunchKernelGGL((pic::k_push<R, D, FUSED, A>), g, b, lds, x->stream, p);
         HIP_OK(hipGetLastError());
         return PIC_OK;
+    }
+
+    static pic_status push(pic_ctx *x, bool fused)
+    {
+        if (!fused) return push_with<false, R>(x);
+        return x->acc_working ? push_with<true, R>(x) : push_with<true, double>(x);
     }
 
     static pic_status deposit(pic_ctx *x, bool unfused_part)
@@ -339,10 +341,17 @@ struct Impl {
         Params<R> p = params<R>(x);
         dim3 g((unsigned)x->L.pub.tiles_total);
         if (unfused_part) {
-            size_t lds = 3 * x->L.jblk_cells * sizeof(R);
-            pic_status st = set_lds(pic::k_deposit<R, D>, lds);
-            if (st) return st;
-            hipLaunchKernelGGL((pic::k_deposit<R, D>), g, dim3(x->block), lds, x->stream, p);
+            if (x->acc_working) {
+                size_t lds = 3 * x->L.jblk_cells * sizeof(R);
+                pic_status st = set_lds(pic::k_deposit<R, D, R>, lds);
+                if (st) return st;
+                hipLaunchKernelGGL((pic::k_deposit<R, D, R>), g, dim3(x->block), lds, x->stream, p);
+            } else {
+                size_t lds = 3 * x->L.jblk_cells * sizeof(double);
+                pic_status st = set_lds(pic::k_deposit<R, D, double>, lds);
+                if (st) return st;
+                hipLaunchKernelGGL((pic::k_deposit<R, D, double>), g, dim3(x->block), lds, x->stream, p);
+            }
             HIP_OK(hipGetLastError());
         }
         hipLaunchKernelGGL((pic::k_fold<R, D>), g, dim3(256), 0, x->stream, p);
@@ -569,6 +578,7 @@ pic_status pic_init_tiles(const pic_config *cfg, const int64_t *counts, void *wo
     x->ns = cfg->n_species;
     x->nb = cfg->n_boxes;
     x->block = cfg->block ? cfg->block : 256;
+    x->acc_working = (cfg->options & PIC_OPT_ACC_WORKING) != 0;
     for (int d = 0; d < 3; ++d) x->T[d] = cfg->tile[d];
     x->c = cfg->cfl;
     x->stream = reinterpret_cast<hipStream_t>(hip_stream);

@@ -82,10 +82,12 @@ __device__ __forceinline__ void latch(int32_t *err, int32_t bits)
     atomicOr(err, bits);
 }
 
-template <typename R>
-__device__ __forceinline__ void lds_add(R *p, R v)
+// LDS atomic add of a value computed in precision R into an accumulator of
+// type A (float or double).
+template <typename A, typename R>
+__device__ __forceinline__ void lds_add(A *p, R v)
 {
-    atomicAdd(p, v);
+    atomicAdd(p, (A)v);
 }
 
 // Field halo block in LDS: local cells -1..T per grid dimension.
@@ -254,15 +256,15 @@ __device__ __forceinline__ void displacement(const R u[3], R c, R dv[3])
 // grid dimension a, to points i_a and i_a+1 with weights 1-W_a and W_a at
 // the segment midpoint; with two transverse dimensions the path average of
 // the product adds sigma_a sigma_b dv_a dv_b / 12.
-template <typename R, int D>
-__device__ __forceinline__ void deposit_segment(R *sJ, const CurBox<D> &cb, const R F[3], const R W[3],
+template <typename R, int D, typename A>
+__device__ __forceinline__ void deposit_segment(A *sJ, const CurBox<D> &cb, const R F[3], const R W[3],
                                                 const R dv[3], const int li[3])
 {
     const int s1 = cb.e0, s2 = cb.e0 * cb.e1;
     int base = li[0];
     if constexpr (D > 1) base += li[1] * s1;
     if constexpr (D > 2) base += li[2] * s2;
-    R *Jx = sJ, *Jy = sJ + cb.n, *Jz = sJ + 2 * cb.n;
+    A *Jx = sJ, *Jy = sJ + cb.n, *Jz = sJ + 2 * cb.n;
     if constexpr (D == 1) {
         lds_add(Jx + base, F[0]);
         lds_add(Jy + base, F[1] * (R(1) - W[0]));
@@ -302,8 +304,8 @@ __device__ __forceinline__ void deposit_segment(R *sJ, const CurBox<D> &cb, cons
 // unrebased) with displacement dv (all three components) and charge q.
 // Relay point per grid dimension: min(min(i1,i2)+1, max(max(i1,i2),
 // (x1+x2)/2)); along non-grid dimensions the two segments share dv/2.
-template <typename R, int D>
-__device__ __forceinline__ void zigzag(R *sJ, const CurBox<D> &cb, const int32_t T[3], const R x1[3], const R x2[3],
+template <typename R, int D, typename A>
+__device__ __forceinline__ void zigzag(A *sJ, const CurBox<D> &cb, const int32_t T[3], const R x1[3], const R x2[3],
                                        const R dv[3], R q)
 {
     R F1[3], F2[3], W1[3] = {0, 0, 0}, W2[3] = {0, 0, 0}, d1[3], d2[3];
@@ -331,8 +333,8 @@ __device__ __forceinline__ void zigzag(R *sJ, const CurBox<D> &cb, const int32_t
             F2[d] = q * h;
         }
     }
-    deposit_segment<R, D>(sJ, cb, F1, W1, d1, l1);
-    deposit_segment<R, D>(sJ, cb, F2, W2, d2, l2);
+    deposit_segment<R, D, A>(sJ, cb, F1, W1, d1, l1);
+    deposit_segment<R, D, A>(sJ, cb, F2, W2, d2, l2);
 }
 
 // Tile offset code sum (delta_d+1) 3^d of a position after the push.

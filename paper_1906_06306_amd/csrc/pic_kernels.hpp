@@ -106,7 +106,11 @@ __device__ __forceinline__ void compact_chunk(const Params<R> &p, int ts, int64_
 // ------------------------------------------------------------------ push
 
 // interp_em + push (+ comp_curr and particle pack when FUSED) for one tile.
-template <typename R, int D, bool FUSED>
+// The current block is accumulated in LDS in type A (FP64 by default: the
+// LDS FP64 atomic add sustains a far higher rate on gfx950 than the FP32
+// one under the many-address pattern of the deposit, and sums more
+// accurately); it is rounded to R once, at the flush.
+template <typename R, int D, bool FUSED, typename A>
 __global__ void __launch_bounds__(1024) k_push(Params<R> p)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -114,12 +118,12 @@ __global__ void __launch_bounds__(1024) k_push(Params<R> p)
     const TileDesc td = p.tiles[t];
     const FieldBox<D> fb(p.T);
     const CurBox<D> cb(p.T);
-    R *sF = reinterpret_cast<R *>(smem);
-    R *sJ = sF + 6 * fb.n;
-    int *sTot = reinterpret_cast<int *>(sJ + (FUSED ? 3 * cb.n : 0));
+    A *sJ = reinterpret_cast<A *>(smem);
+    R *sF = reinterpret_cast<R *>(sJ + (FUSED ? 3 * cb.n : 0));
+    int *sTot = reinterpret_cast<int *>(sF + 6 * fb.n);
     stage_fields<R, D>(p, td, sF, fb);
     if constexpr (FUSED) {
-        for (int k = threadIdx.x; k < 3 * cb.n; k += blockDim.x) sJ[k] = R(0);
+        for (int k = threadIdx.x; k < 3 * cb.n; k += blockDim.x) sJ[k] = A(0);
     }
     __syncthreads();
     const R c = p.c;
@@ -154,7 +158,7 @@ __global__ void __launch_bounds__(1024) k_push(Params<R> p)
                     ok = ok && moved_ok<R, D>(x2, dv, p.T);
                     if (ok) {
                         if constexpr (FUSED) {
-                            zigzag<R, D>(sJ, cb, p.T, x, x2, dv, q);
+                            zigzag<R, D, A>(sJ, cb, p.T, x, x2, dv, q);
                             code = direction_code<R, D>(x2, p.T, delta);
                         }
                     } else {
@@ -191,21 +195,21 @@ __global__ void __launch_bounds__(1024) k_push(Params<R> p)
     if constexpr (FUSED) {
         __syncthreads();
         R *blk = p.jblk + (int64_t)t * 3 * cb.n;
-        for (int k = threadIdx.x; k < 3 * cb.n; k += blockDim.x) blk[k] = sJ[k];
+        for (int k = threadIdx.x; k < 3 * cb.n; k += blockDim.x) blk[k] = (R)sJ[k];
     }
 }
 
 // comp_curr after an unfused push: ZigZag from (xold, pos) of every
 // particle into the tile's current block.
-template <typename R, int D>
+template <typename R, int D, typename A>
 __global__ void __launch_bounds__(1024) k_deposit(Params<R> p)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int t = p.order ? p.order[blockIdx.x] : (int)blockIdx.x;
     const TileDesc td = p.tiles[t];
     const CurBox<D> cb(p.T);
-    R *sJ = reinterpret_cast<R *>(smem);
-    for (int k = threadIdx.x; k < 3 * cb.n; k += blockDim.x) sJ[k] = R(0);
+    A *sJ = reinterpret_cast<A *>(smem);
+    for (int k = threadIdx.x; k < 3 * cb.n; k += blockDim.x) sJ[k] = A(0);
     __syncthreads();
     const int64_t cap = p.cap_total;
     for (int s = 0; s < p.nspecies; ++s) {
@@ -224,12 +228,12 @@ __global__ void __launch_bounds__(1024) k_deposit(Params<R> p)
             for (int m = 0; m < 3; ++m) u[m] = p.u[m * cap + so + i];
             displacement<R>(u, p.c, dv);
             const bool ok = inside_tile<R, D>(x1, p.T) && finite3<R>(u) && moved_ok<R, D>(x2, dv, p.T);
-            if (ok) zigzag<R, D>(sJ, cb, p.T, x1, x2, dv, q);
+            if (ok) zigzag<R, D, A>(sJ, cb, p.T, x1, x2, dv, q);
         }
     }
     __syncthreads();
     R *blk = p.jblk + (int64_t)t * 3 * cb.n;
-    for (int k = threadIdx.x; k < 3 * cb.n; k += blockDim.x) blk[k] = sJ[k];
+    for (int k = threadIdx.x; k < 3 * cb.n; k += blockDim.x) blk[k] = (R)sJ[k];
 }
 
 // cur_exchange: J on the lattice = sum of the current blocks of the tile

@@ -37,7 +37,7 @@ class PicSim:
     """A batch of periodic boxes stepped together on one GPU."""
 
     def __init__(self, boxes, tile, precision: str = "fp32", block: int = 256, capacity_factor: float = 1.25,
-                 tile_capacity=None, outbox_capacity: int = 0, device: str = "cuda:0"):
+                 tile_capacity=None, outbox_capacity: int = 0, options: int = 0, device: str = "cuda:0"):
         if not isinstance(boxes, (list, tuple)):
             boxes = [boxes]
         boxes = [b if isinstance(b, Box) else box_from_plasma(b) for b in boxes]
@@ -78,6 +78,7 @@ class PicSim:
         cfg.tile_capacity = None if self._tcap is None else self._tcap.ctypes.data
         cfg.capacity_factor = capacity_factor
         cfg.outbox_capacity = outbox_capacity
+        cfg.options = options
         self.cfg = cfg
         lay = L.PicLayout()
         L.check(lib.pic_query(ctypes.byref(cfg), self._counts.ctypes.data, ctypes.byref(lay)))
