@@ -78,15 +78,18 @@ def run_gpu(plasma, args, precision, steps, warmup, profile_only=False):
     lib = L.lib()
     ctx = sim.ctx
 
+    flags = L.PIC_FUSED | L.PIC_PUSH_HALF_B
+
     def step(ev=None):
-        L.check(lib.pic_fdtd_step(ctx, L.PIC_HALF_B))
+        # the sequence pic_step(PIC_FUSED | PIC_PUSH_HALF_B) enqueues, with
+        # events around the fused push
         if ev is not None:
             ev[0].record(stream)
-        L.check(lib.pic_push_interp(ctx, L.PIC_FUSED))
+        L.check(lib.pic_push_interp(ctx, flags))
         if ev is not None:
             ev[1].record(stream)
-        L.check(lib.pic_fdtd_step(ctx, L.PIC_HALF_B))
-        L.check(lib.pic_deposit_current(ctx, L.PIC_FUSED))
+        L.check(lib.pic_fdtd_step(ctx, L.PIC_TWO_HALF_B))
+        L.check(lib.pic_deposit_current(ctx, flags))
         L.check(lib.pic_fdtd_step(ctx, L.PIC_CURL_E_ADD_J))
         L.check(lib.pic_sort_migrate(ctx, 0))
 

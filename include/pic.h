@@ -12,7 +12,9 @@
  *                                      cur_exchange            App. D
  *   pic_fdtd_step(PIC_CURL_E_ADD_J)    push_e + add_cur        Eq. (fdE)
  *   pic_sort_migrate(...)              particle communication rows
- * pic_step() enqueues exactly that sequence.
+ * pic_step() enqueues exactly that sequence; with PIC_PUSH_HALF_B the
+ * first half update runs inside the push (on its LDS copy of B) and both
+ * halves are applied to the stored B by one PIC_TWO_HALF_B pass.
  *
  * Units (App. A): dx = dt = 1, Courant number c = cfl; E, B, J in code
  * units; four-velocities u in units of the speed of light.
@@ -80,10 +82,15 @@ typedef int32_t pic_status;
 #define PIC_CURL_E 1        /* E += c curl- B            push_e           */
 #define PIC_ADD_J 2         /* E -= J                    add_cur          */
 #define PIC_CURL_E_ADD_J 3  /* both, one pass (they commute)              */
+#define PIC_TWO_HALF_B 4    /* push_half_b1 then push_half_b2 in one pass:
+                               B -= (c/2) curl+ E twice, E unchanged between */
 
 /* flags of pic_push_interp / pic_deposit_current / pic_sort_migrate */
 #define PIC_FUSED 1u        /* push also deposits J and moves leavers out  */
 #define PIC_SORT_CELLS 2u   /* stable sort by cell inside every tile        */
+#define PIC_PUSH_HALF_B 4u  /* the push applies push_half_b1 to its own LDS
+                               copy of B; stored B stays at B^{n-1/2}, and
+                               the caller then uses PIC_TWO_HALF_B          */
 
 typedef struct {
     int32_t dim;          /* spatial dimensions D in {1,2,3}                 */
@@ -185,7 +192,7 @@ pic_status pic_init_tiles(const pic_config *cfg, const int64_t *counts, void *wo
 
 /* Field update on every box (Eqs. fdE/fdB with the forward and backward
  * differences of App. B; periodic).  phase: PIC_HALF_B, PIC_CURL_E,
- * PIC_ADD_J or PIC_CURL_E_ADD_J. */
+ * PIC_ADD_J, PIC_CURL_E_ADD_J or PIC_TWO_HALF_B. */
 pic_status pic_fdtd_step(pic_ctx *ctx, int32_t phase);
 
 /* interp_em + push for every particle: linear interpolation of each E and B

@@ -22,8 +22,10 @@ PIC_HALF_B = 0
 PIC_CURL_E = 1
 PIC_ADD_J = 2
 PIC_CURL_E_ADD_J = 3
+PIC_TWO_HALF_B = 4
 PIC_FUSED = 1
 PIC_SORT_CELLS = 2
+PIC_PUSH_HALF_B = 4
 PIC_OPT_ACC_WORKING = 1
 
 EXPORTS = ["pic_query", "pic_init_tiles", "pic_fdtd_step", "pic_push_interp", "pic_deposit_current",

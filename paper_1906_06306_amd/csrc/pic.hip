@@ -19,6 +19,11 @@
 using pic::Params;
 using pic::TileDesc;
 
+// particles per thread per group in the fused push kernel
+#ifndef PUSH_UNROLL
+#define PUSH_UNROLL 1
+#endif
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -49,7 +54,7 @@ struct Layout {
     uint64_t off_tmp, off_jblk, off_rblk, off_part, off_ob_pos, off_ob_u, off_ob_dir, off_ob_cnt;
     uint64_t off_tiles, off_charge, off_qm, off_mass, off_order, off_queue;
     uint64_t off_key, off_xl, off_hist;
-    int64_t jblk_cells, rblk_cells, max_count, max_ntb, nchunks_max;
+    int64_t jblk_cells, rblk_cells, max_count, max_ntb, nchunks_max, ob_dir_stride;
     std::vector<TileDesc> tiles;
     std::vector<int64_t> seg_off;
     std::vector<int32_t> seg_cap;
@@ -129,7 +134,10 @@ pic_status make_layout(const pic_config *c, const int64_t *counts, Layout &L)
     }
     if (L.max_ntb > 32768) return fail(PIC_E_ARG, "a box has %lld tiles; at most 32768 are supported", (long long)L.max_ntb);
     if (tiles > INT32_MAX / 8) return fail(PIC_E_ARG, "too many tiles");
-    // segment capacities
+    // segment capacities: a multiple of the push kernel's group (threads x
+    // particles per thread), so every lane of the last group of a segment
+    // has a slot of its own to load from and store to
+    const int64_t group = (int64_t)PUSH_UNROLL * (c->block ? c->block : 256);
     double factor = c->capacity_factor > 0 ? c->capacity_factor : 1.25;
     L.seg_off.assign(tiles * ns, 0);
     L.seg_cap.assign(tiles * ns, 0);
@@ -141,10 +149,10 @@ pic_status make_layout(const pic_config *c, const int64_t *counts, Layout &L)
         for (int s = 0; s < ns; ++s) {
             int64_t cap;
             if (c->tile_capacity) {
-                cap = round_up(std::max<int64_t>(c->tile_capacity[t * ns + s], 64), 64);
+                cap = round_up(std::max<int64_t>(c->tile_capacity[t * ns + s], 64), group);
             } else {
                 double expect = (double)counts[b * ns + s] / (double)ntb;
-                cap = round_up((int64_t)std::ceil(factor * expect) + 64, 64);
+                cap = round_up((int64_t)std::ceil(factor * expect) + 64, group);
             }
             if (cap > INT32_MAX / 2) return fail(PIC_E_ARG, "segment capacity too large");
             L.seg_off[t * ns + s] = cap_total;
@@ -195,7 +203,8 @@ pic_status make_layout(const pic_config *c, const int64_t *counts, Layout &L)
     L.off_part = take(tiles * pic::NPART * 8);
     L.off_ob_pos = take(tiles * ns * obcap * D * w);
     L.off_ob_u = take(tiles * ns * obcap * 3 * w);
-    L.off_ob_dir = take(tiles * ns * obcap * 4);
+    L.ob_dir_stride = obcap + group;   // padding slots take the codes of stayers
+    L.off_ob_dir = take(tiles * ns * L.ob_dir_stride * 4);
     L.off_ob_cnt = take(tiles * ns * 4);
     L.off_tiles = take(tiles * sizeof(TileDesc));
     L.off_charge = take(nb * ns * w);
@@ -242,6 +251,7 @@ Params<R> params(pic_ctx *x)
     p.nspecies = x->ns;
     for (int d = 0; d < 3; ++d) p.T[d] = x->T[d];
     p.c = (R)x->c;
+    p.inv_c = (R)(1.0 / x->c);
     p.charge = reinterpret_cast<const R *>(ws + L.off_charge);
     p.qm = reinterpret_cast<const R *>(ws + L.off_qm);
     p.E = reinterpret_cast<R *>(ws + L.pub.off_E);
@@ -261,6 +271,7 @@ Params<R> params(pic_ctx *x)
     p.ob_dir = reinterpret_cast<int32_t *>(ws + L.off_ob_dir);
     p.ob_cnt = reinterpret_cast<int32_t *>(ws + L.off_ob_cnt);
     p.ob_cap = L.pub.outbox_capacity;
+    p.ob_dir_stride = L.ob_dir_stride;
     p.tmp = reinterpret_cast<R *>(ws + L.off_tmp);
     p.err = reinterpret_cast<int32_t *>(ws + L.pub.off_error);
     p.nearface = reinterpret_cast<unsigned long long *>(ws + L.pub.off_flags);
@@ -298,7 +309,8 @@ struct Impl {
             fbn *= x->T[d] + 2;
             cbn *= x->T[d] + 3;
         }
-        return 6 * fbn * sizeof(R) + (fused ? 3 * cbn * acc_bytes : 0) + 2 * pic::MAX_WAVES * sizeof(int);
+        return (3 * cbn + 3 * fbn) * sizeof(R) + (fused ? 3 * cbn * acc_bytes : 0) +
+               2 * PUSH_UNROLL * pic::MAX_WAVES * sizeof(int);
     }
 
     static pic_status fdtd(pic_ctx *x, int phase)
@@ -311,29 +323,31 @@ struct Impl {
         case PIC_CURL_E: hipLaunchKernelGGL((pic::k_field<R, D, 1>), g, b, 0, x->stream, p, c); break;
         case PIC_ADD_J: hipLaunchKernelGGL((pic::k_field<R, D, 2>), g, b, 0, x->stream, p, c); break;
         case PIC_CURL_E_ADD_J: hipLaunchKernelGGL((pic::k_field<R, D, 3>), g, b, 0, x->stream, p, c); break;
+        case PIC_TWO_HALF_B: hipLaunchKernelGGL((pic::k_field<R, D, 4>), g, b, 0, x->stream, p, R(0.5) * c); break;
         default: return fail(PIC_E_ARG, "unknown fdtd phase %d", phase);
         }
         HIP_OK(hipGetLastError());
         return PIC_OK;
     }
 
-    template <bool FUSED, typename A>
+    template <bool FUSED, bool HALFB, typename A>
     static pic_status push_with(pic_ctx *x)
     {
         Params<R> p = params<R>(x);
         size_t lds = push_lds(x, FUSED, sizeof(A));
         dim3 g((unsigned)x->L.pub.tiles_total), b(x->block);
-        pic_status st = set_lds(pic::k_push<R, D, FUSED, A>, lds);
+        pic_status st = set_lds(pic::k_push<R, D, FUSED, HALFB, A, PUSH_UNROLL>, lds);
         if (st) return st;
-        hipLaunchKernelGGL((pic::k_push<R, D, FUSED, A>), g, b, lds, x->stream, p);
+        hipLaunchKernelGGL((pic::k_push<R, D, FUSED, HALFB, A, PUSH_UNROLL>), g, b, lds, x->stream, p);
         HIP_OK(hipGetLastError());
         return PIC_OK;
     }
 
-    static pic_status push(pic_ctx *x, bool fused)
+    static pic_status push(pic_ctx *x, bool fused, bool halfb)
     {
-        if (!fused) return push_with<false, R>(x);
-        return x->acc_working ? push_with<true, R>(x) : push_with<true, double>(x);
+        if (!fused) return halfb ? push_with<false, true, R>(x) : push_with<false, false, R>(x);
+        if (x->acc_working) return halfb ? push_with<true, true, R>(x) : push_with<true, false, R>(x);
+        return halfb ? push_with<true, true, double>(x) : push_with<true, false, double>(x);
     }
 
     static pic_status deposit(pic_ctx *x, bool unfused_part)
@@ -497,7 +511,7 @@ struct Impl {
 
 pic_status do_init(pic_ctx *x, const int64_t *counts, const pic_init_data *in) { PIC_DISPATCH(x, init(x, counts, in)); }
 pic_status do_fdtd(pic_ctx *x, int phase) { PIC_DISPATCH(x, fdtd(x, phase)); }
-pic_status do_push(pic_ctx *x, bool fused) { PIC_DISPATCH(x, push(x, fused)); }
+pic_status do_push(pic_ctx *x, bool fused, bool halfb) { PIC_DISPATCH(x, push(x, fused, halfb)); }
 pic_status do_deposit(pic_ctx *x, bool unfused) { PIC_DISPATCH(x, deposit(x, unfused)); }
 pic_status do_migrate(pic_ctx *x, bool out, bool in, bool sort) { PIC_DISPATCH(x, migrate(x, out, in, sort)); }
 pic_status do_diag(pic_ctx *x, pic_diag *o) { PIC_DISPATCH(x, diag(x, o)); }
@@ -625,7 +639,7 @@ pic_status pic_push_interp(pic_ctx *x, uint32_t flags)
     if (!x) return fail(PIC_E_ARG, "null context");
     if (x->state != 0) return fail(PIC_E_STATE, "push called before the previous push was deposited and migrated");
     const bool fused = flags & PIC_FUSED;
-    pic_status st = do_push(x, fused);
+    pic_status st = do_push(x, fused, (flags & PIC_PUSH_HALF_B) != 0);
     if (st) return st;
     x->state = fused ? 2 : 1;
     return PIC_OK;
@@ -662,6 +676,15 @@ pic_status pic_sort_migrate(pic_ctx *x, uint32_t flags)
 pic_status pic_step(pic_ctx *x, uint32_t flags)
 {
     pic_status st;
+    if (flags & PIC_PUSH_HALF_B) {
+        // push_half_b1 happens inside the push on its LDS copy of B; both
+        // half updates are then applied to the stored B in one pass
+        if ((st = pic_push_interp(x, flags))) return st;
+        if ((st = pic_fdtd_step(x, PIC_TWO_HALF_B))) return st;
+        if ((st = pic_deposit_current(x, flags))) return st;
+        if ((st = pic_fdtd_step(x, PIC_CURL_E_ADD_J))) return st;
+        return pic_sort_migrate(x, flags);
+    }
     if ((st = pic_fdtd_step(x, PIC_HALF_B))) return st;
     if ((st = pic_push_interp(x, flags))) return st;
     if ((st = pic_fdtd_step(x, PIC_HALF_B))) return st;

@@ -34,6 +34,7 @@ struct Params {
     int32_t T[3];
     int32_t pad0;
     R c;                      // Courant number
+    R inv_c;                  // 1 / c
     const R *charge;          // [box][species]
     const R *qm;              // [box][species] App. C factor s
     R *E, *B, *J;             // [3][cells_total]
@@ -45,9 +46,10 @@ struct Params {
     int32_t *seg_cnt;
     R *jblk;                  // [tile][3][JV]
     R *ob_pos, *ob_u;         // [tile*species][D|3][ob_cap]
-    int32_t *ob_dir;          // [tile*species][ob_cap]
+    int32_t *ob_dir;          // [tile*species][ob_dir_stride]
     int32_t *ob_cnt;          // [tile*species]
     int64_t ob_cap;
+    int64_t ob_dir_stride;    // ob_cap plus padding slots
     R *tmp;                   // sort staging [(D+3)][cap_total]
     int32_t *err;             // latched error bits
     unsigned long long *nearface;
@@ -80,6 +82,18 @@ __device__ __forceinline__ int lanes_below(unsigned long long mask)
 __device__ __forceinline__ void latch(int32_t *err, int32_t bits)
 {
     atomicOr(err, bits);
+}
+
+// OR the per-thread error bits of a wave into the device word with one
+// atomic (called by every lane of the wave): a burst of failing particles
+// then costs one atomic per wave instead of one per particle.
+__device__ __forceinline__ void latch_wave(int32_t *err, int32_t bits)
+{
+    const unsigned long long any = __ballot(bits != 0);
+    if (!any) return;
+    int v = bits;
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o);
+    if ((int)(threadIdx.x & 63) == __ffsll((long long)any) - 1) atomicOr(err, v);
 }
 
 // LDS atomic add of a value computed in precision R into an accumulator of
@@ -118,23 +132,41 @@ struct CurBox {
     }
 };
 
-// Copy E and B of the tile plus a one-cell halo into LDS (periodic wrap).
-// sF layout: [6][fb.n], component order Ex Ey Ez Bx By Bz.
-template <typename R, int D>
-__device__ void stage_fields(const Params<R> &p, const TileDesc &td, R *sF, const FieldBox<D> &fb)
+// Copy E (local cells -1..T+1) and B (local cells -1..T) of the tile into
+// LDS, periodic wrap.  sE layout [3][cb.n], sB layout [3][fb.n].
+template <typename R, int D, typename BoxT>
+__device__ __forceinline__ void stage_block(const R *__restrict__ src, int64_t N, const TileDesc &td,
+                                            const int32_t T[3], R *dst, const BoxT &bx)
 {
     const int n0 = td.n[0], n1 = td.n[1], n2 = td.n[2];
-    for (int k = threadIdx.x; k < fb.n; k += blockDim.x) {
-        int lx = k % fb.e0, ly = (k / fb.e0) % fb.e1, lz = k / (fb.e0 * fb.e1);
-        int gx = D > 0 ? wrapi(td.tc[0] * p.T[0] + lx - 1, n0) : 0;
-        int gy = D > 1 ? wrapi(td.tc[1] * p.T[1] + ly - 1, n1) : 0;
-        int gz = D > 2 ? wrapi(td.tc[2] * p.T[2] + lz - 1, n2) : 0;
+    for (int k = threadIdx.x; k < bx.n; k += blockDim.x) {
+        int lx = k % bx.e0, ly = (k / bx.e0) % bx.e1, lz = k / (bx.e0 * bx.e1);
+        int gx = D > 0 ? wrapi(td.tc[0] * T[0] + lx - 1, n0) : 0;
+        int gy = D > 1 ? wrapi(td.tc[1] * T[1] + ly - 1, n1) : 0;
+        int gz = D > 2 ? wrapi(td.tc[2] * T[2] + lz - 1, n2) : 0;
         int64_t g = td.cell0 + gx + (int64_t)n0 * (gy + (int64_t)n1 * gz);
 #pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            sF[m * fb.n + k] = p.E[m * p.cells_total + g];
-            sF[(3 + m) * fb.n + k] = p.B[m * p.cells_total + g];
-        }
+        for (int m = 0; m < 3; ++m) dst[m * bx.n + k] = src[m * N + g];
+    }
+}
+
+// First half of the B advance (push_half_b1) applied to the LDS copy of B:
+// B -= h curl+ E on local cells -1..T, from the staged E (cells -1..T+1).
+template <typename R, int D>
+__device__ __forceinline__ void half_b_lds(R *sB, const FieldBox<D> &fb, const R *sE, const CurBox<D> &cb, R h)
+{
+    for (int k = threadIdx.x; k < fb.n; k += blockDim.x) {
+        const int lx = k % fb.e0, ly = (k / fb.e0) % fb.e1, lz = k / (fb.e0 * fb.e1);
+        const int e = lx + cb.e0 * (ly + cb.e1 * lz);
+        const int ip = D > 0 ? 1 : 0, jp = D > 1 ? cb.e0 : 0, kp = D > 2 ? cb.e0 * cb.e1 : 0;
+        const R *Ex = sE, *Ey = sE + cb.n, *Ez = sE + 2 * cb.n;
+        const R ex = Ex[e], ey = Ey[e], ez = Ez[e];
+        const R cx = (Ez[e + jp] - ez) - (Ey[e + kp] - ey);
+        const R cy = (Ex[e + kp] - ex) - (Ez[e + ip] - ez);
+        const R cz = (Ey[e + ip] - ey) - (Ex[e + jp] - ex);
+        sB[k] -= h * cx;
+        sB[fb.n + k] -= h * cy;
+        sB[2 * fb.n + k] -= h * cz;
     }
 }
 
@@ -200,103 +232,161 @@ __device__ __forceinline__ R interp_comp(const R *__restrict__ F, int s1, int s2
 }
 
 template <typename R, int D>
-__device__ __forceinline__ void interp_all(const R *sF, const FieldBox<D> &fb, const R x[3], const int32_t T[3],
-                                           R e[3], R b[3])
+__device__ __forceinline__ void interp_all(const R *sE, const CurBox<D> &cb, const R *sB, const FieldBox<D> &fb,
+                                           const R x[3], const int32_t T[3], R e[3], R b[3])
 {
     Stencil<R, D> st;
     make_stencil<R, D>(x, T, st);
-    const int s1 = fb.e0, s2 = fb.e0 * fb.e1;
-    e[0] = interp_comp<R, D, 0>(sF + 0 * fb.n, s1, s2, st);
-    e[1] = interp_comp<R, D, 1>(sF + 1 * fb.n, s1, s2, st);
-    e[2] = interp_comp<R, D, 2>(sF + 2 * fb.n, s1, s2, st);
-    b[0] = interp_comp<R, D, 3>(sF + 3 * fb.n, s1, s2, st);
-    b[1] = interp_comp<R, D, 4>(sF + 4 * fb.n, s1, s2, st);
-    b[2] = interp_comp<R, D, 5>(sF + 5 * fb.n, s1, s2, st);
+    const int e1 = cb.e0, e2 = cb.e0 * cb.e1;
+    const int f1 = fb.e0, f2 = fb.e0 * fb.e1;
+    e[0] = interp_comp<R, D, 0>(sE + 0 * cb.n, e1, e2, st);
+    e[1] = interp_comp<R, D, 1>(sE + 1 * cb.n, e1, e2, st);
+    e[2] = interp_comp<R, D, 2>(sE + 2 * cb.n, e1, e2, st);
+    b[0] = interp_comp<R, D, 3>(sB + 0 * fb.n, f1, f2, st);
+    b[1] = interp_comp<R, D, 4>(sB + 1 * fb.n, f1, f2, st);
+    b[2] = interp_comp<R, D, 5>(sB + 2 * fb.n, f1, f2, st);
 }
 
 // ------------------------------------------------------------------ Boris
 
-// Relativistic Boris update (App. C) of u^{n-1/2} -> u^{n+1/2}; velocities
-// inside the update are carried in units of the Courant number.
+// Reciprocal and reciprocal square root in the working precision.  FP32
+// uses the hardware v_rcp_f32 / v_rsq_f32 (about 1 ulp), which the FP32
+// tolerance of the method admits; FP64 keeps correctly rounded division and
+// square root.
 template <typename R>
-__device__ __forceinline__ void boris(R u[3], const R e[3], const R b[3], R c, R s)
+__device__ __forceinline__ R rcp_w(R x);
+template <>
+__device__ __forceinline__ float rcp_w<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <>
+__device__ __forceinline__ double rcp_w<double>(double x) { return 1.0 / x; }
+template <typename R>
+__device__ __forceinline__ R rsqrt_w(R x);
+template <>
+__device__ __forceinline__ float rsqrt_w<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <>
+__device__ __forceinline__ double rsqrt_w<double>(double x) { return 1.0 / sqrt(x); }
+
+// Relativistic Boris update (App. C) of u^{n-1/2} -> u^{n+1/2}; velocities
+// inside the update are carried in units of the Courant number c
+// (inv_c = 1/c): u1 = c u + s E/2, gamma1 = sqrt(1 + |u1|^2/c^2),
+// t = s B/(2 c gamma1), f = 2/(1+|t|^2), u2 = f (u1 + u1 x t),
+// u3 = u1 + u2 x t + s E/2, u = u3/c.
+template <typename R>
+__device__ __forceinline__ void boris(R u[3], const R e[3], const R b[3], R c, R inv_c, R s)
 {
     const R hs = R(0.5) * s;
     R ex = hs * e[0], ey = hs * e[1], ez = hs * e[2];
     R u1x = c * u[0] + ex, u1y = c * u[1] + ey, u1z = c * u[2] + ez;
-    R g1 = sqrt(R(1) + (u1x * u1x + u1y * u1y + u1z * u1z) / (c * c));
-    R k = s / (R(2) * c * g1);
+    R k = (hs * inv_c) * rsqrt_w<R>(R(1) + (u1x * u1x + u1y * u1y + u1z * u1z) * (inv_c * inv_c));
     R tx = k * b[0], ty = k * b[1], tz = k * b[2];
-    R f = R(2) / (R(1) + (tx * tx + ty * ty + tz * tz));
+    R f = R(2) * rcp_w<R>(R(1) + (tx * tx + ty * ty + tz * tz));
     R u2x = f * (u1x + (u1y * tz - u1z * ty));
     R u2y = f * (u1y + (u1z * tx - u1x * tz));
     R u2z = f * (u1z + (u1x * ty - u1y * tx));
     R u3x = u1x + (u2y * tz - u2z * ty) + ex;
     R u3y = u1y + (u2z * tx - u2x * tz) + ey;
     R u3z = u1z + (u2x * ty - u2y * tx) + ez;
-    u[0] = u3x / c;
-    u[1] = u3y / c;
-    u[2] = u3z / c;
+    u[0] = u3x * inv_c;
+    u[1] = u3y * inv_c;
+    u[2] = u3z * inv_c;
 }
 
 // Eq. (fdX): displacement c u / gamma of u^{n+1/2}, all three components.
 template <typename R>
 __device__ __forceinline__ void displacement(const R u[3], R c, R dv[3])
 {
-    R g = sqrt(R(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    dv[0] = c * u[0] / g;
-    dv[1] = c * u[1] / g;
-    dv[2] = c * u[2] / g;
+    R r = c * rsqrt_w<R>(R(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    dv[0] = u[0] * r;
+    dv[1] = u[1] * r;
+    dv[2] = u[2] * r;
 }
 
 // ----------------------------------------------------------------- ZigZag
 
-// Deposit one straight segment inside one cell into the LDS current block:
-// component m goes to the cell index along m and, along each transverse
-// grid dimension a, to points i_a and i_a+1 with weights 1-W_a and W_a at
-// the segment midpoint; with two transverse dimensions the path average of
-// the product adds sigma_a sigma_b dv_a dv_b / 12.
-template <typename R, int D, typename A>
-__device__ __forceinline__ void deposit_segment(A *sJ, const CurBox<D> &cb, const R F[3], const R W[3],
-                                                const R dv[3], const int li[3])
+// Current of one straight segment inside one cell, as the values it adds
+// to the LDS current block: component m goes to the cell index along m and,
+// along each transverse grid dimension a, to points i_a and i_a+1 with
+// weights 1-W_a and W_a at the segment midpoint; with two transverse
+// dimensions the path average of the product adds
+// sigma_a sigma_b dv_a dv_b / 12.  Value order matches seg_offset().
+template <int D>
+__host__ __device__ constexpr int seg_values()
 {
-    const int s1 = cb.e0, s2 = cb.e0 * cb.e1;
-    int base = li[0];
-    if constexpr (D > 1) base += li[1] * s1;
-    if constexpr (D > 2) base += li[2] * s2;
-    A *Jx = sJ, *Jy = sJ + cb.n, *Jz = sJ + 2 * cb.n;
+    return D == 1 ? 5 : (D == 2 ? 8 : 12);
+}
+
+template <typename R, int D>
+__device__ __forceinline__ void segment_values(const R F[3], const R W[3], const R dv[3], R v[seg_values<D>()])
+{
     if constexpr (D == 1) {
-        lds_add(Jx + base, F[0]);
-        lds_add(Jy + base, F[1] * (R(1) - W[0]));
-        lds_add(Jy + base + 1, F[1] * W[0]);
-        lds_add(Jz + base, F[2] * (R(1) - W[0]));
-        lds_add(Jz + base + 1, F[2] * W[0]);
+        v[0] = F[0];
+        v[1] = F[1] * (R(1) - W[0]);
+        v[2] = F[1] * W[0];
+        v[3] = F[2] * (R(1) - W[0]);
+        v[4] = F[2] * W[0];
     } else if constexpr (D == 2) {
-        lds_add(Jx + base, F[0] * (R(1) - W[1]));
-        lds_add(Jx + base + s1, F[0] * W[1]);
-        lds_add(Jy + base, F[1] * (R(1) - W[0]));
-        lds_add(Jy + base + 1, F[1] * W[0]);
-        R cr = dv[0] * dv[1] / R(12);
-        lds_add(Jz + base, F[2] * ((R(1) - W[0]) * (R(1) - W[1]) + cr));
-        lds_add(Jz + base + 1, F[2] * (W[0] * (R(1) - W[1]) - cr));
-        lds_add(Jz + base + s1, F[2] * ((R(1) - W[0]) * W[1] - cr));
-        lds_add(Jz + base + s1 + 1, F[2] * (W[0] * W[1] + cr));
+        v[0] = F[0] * (R(1) - W[1]);
+        v[1] = F[0] * W[1];
+        v[2] = F[1] * (R(1) - W[0]);
+        v[3] = F[1] * W[0];
+        const R cr = dv[0] * dv[1] * R(1.0 / 12.0);
+        v[4] = F[2] * ((R(1) - W[0]) * (R(1) - W[1]) + cr);
+        v[5] = F[2] * (W[0] * (R(1) - W[1]) - cr);
+        v[6] = F[2] * ((R(1) - W[0]) * W[1] - cr);
+        v[7] = F[2] * (W[0] * W[1] + cr);
     } else {
-        R cyz = dv[1] * dv[2] / R(12);
-        lds_add(Jx + base, F[0] * ((R(1) - W[1]) * (R(1) - W[2]) + cyz));
-        lds_add(Jx + base + s1, F[0] * (W[1] * (R(1) - W[2]) - cyz));
-        lds_add(Jx + base + s2, F[0] * ((R(1) - W[1]) * W[2] - cyz));
-        lds_add(Jx + base + s1 + s2, F[0] * (W[1] * W[2] + cyz));
-        R cxz = dv[0] * dv[2] / R(12);
-        lds_add(Jy + base, F[1] * ((R(1) - W[0]) * (R(1) - W[2]) + cxz));
-        lds_add(Jy + base + 1, F[1] * (W[0] * (R(1) - W[2]) - cxz));
-        lds_add(Jy + base + s2, F[1] * ((R(1) - W[0]) * W[2] - cxz));
-        lds_add(Jy + base + 1 + s2, F[1] * (W[0] * W[2] + cxz));
-        R cxy = dv[0] * dv[1] / R(12);
-        lds_add(Jz + base, F[2] * ((R(1) - W[0]) * (R(1) - W[1]) + cxy));
-        lds_add(Jz + base + 1, F[2] * (W[0] * (R(1) - W[1]) - cxy));
-        lds_add(Jz + base + s1, F[2] * ((R(1) - W[0]) * W[1] - cxy));
-        lds_add(Jz + base + s1 + 1, F[2] * (W[0] * W[1] + cxy));
+        const R cyz = dv[1] * dv[2] * R(1.0 / 12.0);
+        v[0] = F[0] * ((R(1) - W[1]) * (R(1) - W[2]) + cyz);
+        v[1] = F[0] * (W[1] * (R(1) - W[2]) - cyz);
+        v[2] = F[0] * ((R(1) - W[1]) * W[2] - cyz);
+        v[3] = F[0] * (W[1] * W[2] + cyz);
+        const R cxz = dv[0] * dv[2] * R(1.0 / 12.0);
+        v[4] = F[1] * ((R(1) - W[0]) * (R(1) - W[2]) + cxz);
+        v[5] = F[1] * (W[0] * (R(1) - W[2]) - cxz);
+        v[6] = F[1] * ((R(1) - W[0]) * W[2] - cxz);
+        v[7] = F[1] * (W[0] * W[2] + cxz);
+        const R cxy = dv[0] * dv[1] * R(1.0 / 12.0);
+        v[8] = F[2] * ((R(1) - W[0]) * (R(1) - W[1]) + cxy);
+        v[9] = F[2] * (W[0] * (R(1) - W[1]) - cxy);
+        v[10] = F[2] * ((R(1) - W[0]) * W[1] - cxy);
+        v[11] = F[2] * (W[0] * W[1] + cxy);
+    }
+}
+
+// LDS offsets (relative to the segment's cell) of those values: component
+// plane offset plus corner offset.
+template <int D>
+__device__ __forceinline__ int seg_offset(const CurBox<D> &cb, int k)
+{
+    const int s1 = cb.e0, s2 = cb.e0 * cb.e1, n = cb.n;
+    if constexpr (D == 1) {
+        return k == 0 ? 0 : (k == 1 ? n : (k == 2 ? n + 1 : (k == 3 ? 2 * n : 2 * n + 1)));
+    } else if constexpr (D == 2) {
+        switch (k) {
+        case 0: return 0;
+        case 1: return s1;
+        case 2: return n;
+        case 3: return n + 1;
+        case 4: return 2 * n;
+        case 5: return 2 * n + 1;
+        case 6: return 2 * n + s1;
+        default: return 2 * n + s1 + 1;
+        }
+    } else {
+        switch (k) {
+        case 0: return 0;
+        case 1: return s1;
+        case 2: return s2;
+        case 3: return s1 + s2;
+        case 4: return n;
+        case 5: return n + 1;
+        case 6: return n + s2;
+        case 7: return n + 1 + s2;
+        case 8: return 2 * n;
+        case 9: return 2 * n + 1;
+        case 10: return 2 * n + s1;
+        default: return 2 * n + s1 + 1;
+        }
     }
 }
 
@@ -304,12 +394,15 @@ __device__ __forceinline__ void deposit_segment(A *sJ, const CurBox<D> &cb, cons
 // unrebased) with displacement dv (all three components) and charge q.
 // Relay point per grid dimension: min(min(i1,i2)+1, max(max(i1,i2),
 // (x1+x2)/2)); along non-grid dimensions the two segments share dv/2.
+// When both segments lie in the same cell they touch the same points, so
+// their values are added in registers and written with one set of atomics.
 template <typename R, int D, typename A>
 __device__ __forceinline__ void zigzag(A *sJ, const CurBox<D> &cb, const int32_t T[3], const R x1[3], const R x2[3],
                                        const R dv[3], R q)
 {
     R F1[3], F2[3], W1[3] = {0, 0, 0}, W2[3] = {0, 0, 0}, d1[3], d2[3];
     int l1[3] = {0, 0, 0}, l2[3] = {0, 0, 0};
+    bool same = true;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         if (d < D) {
@@ -325,6 +418,7 @@ __device__ __forceinline__ void zigzag(A *sJ, const CurBox<D> &cb, const int32_t
             W2[d] = R(0.5) * (b + xr) - fb;
             l1[d] = (int)fa + T[d] / 2 + 1;
             l2[d] = (int)fb + T[d] / 2 + 1;
+            same = same && fa == fb;
         } else {
             R h = R(0.5) * dv[d];
             d1[d] = h;
@@ -333,8 +427,19 @@ __device__ __forceinline__ void zigzag(A *sJ, const CurBox<D> &cb, const int32_t
             F2[d] = q * h;
         }
     }
-    deposit_segment<R, D, A>(sJ, cb, F1, W1, d1, l1);
-    deposit_segment<R, D, A>(sJ, cb, F2, W2, d2, l2);
+    constexpr int NV = seg_values<D>();
+    R v1[NV], v2[NV];
+    segment_values<R, D>(F1, W1, d1, v1);
+    segment_values<R, D>(F2, W2, d2, v2);
+    const int s1 = cb.e0, s2 = cb.e0 * cb.e1;
+    const int b1 = l1[0] + (D > 1 ? l1[1] * s1 : 0) + (D > 2 ? l1[2] * s2 : 0);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) lds_add(sJ + b1 + seg_offset<D>(cb, k), same ? v1[k] + v2[k] : v1[k]);
+    if (!same) {
+        const int b2 = l2[0] + (D > 1 ? l2[1] * s1 : 0) + (D > 2 ? l2[2] * s2 : 0);
+#pragma unroll
+        for (int k = 0; k < NV; ++k) lds_add(sJ + b2 + seg_offset<D>(cb, k), v2[k]);
+    }
 }
 
 // Tile offset code sum (delta_d+1) 3^d of a position after the push.

@@ -32,6 +32,33 @@ __device__ __forceinline__ int wg_scan_flag(bool flag, int *sTot, int parity, in
     return off + below;
 }
 
+// Exclusive prefix of U flags per thread over the work-group, in (j, thread)
+// order: flag j of thread t is element j*blockDim + t.  sTot holds
+// 2*U*MAX_WAVES ints; the halves alternate by `parity` (one barrier).
+template <int U>
+__device__ __forceinline__ int wg_scan_flags(const bool f[U], int *sTot, int parity, int pre[U])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int *tot = sTot + parity * U * MAX_WAVES;
+    int below[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        unsigned long long m = __ballot(f[j]);
+        below[j] = lanes_below(m);
+        if (lane == 0) tot[j * MAX_WAVES + wave] = __popcll(m);
+    }
+    __syncthreads();
+    int run = 0;
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        for (int w = 0; w < nw; ++w) {
+            if (w == wave) pre[j] = run + below[j];
+            run += tot[j * MAX_WAVES + w];
+        }
+    }
+    return run;
+}
+
 template <typename R, int D>
 __device__ __forceinline__ bool inside_tile(const R x[3], const int32_t T[3])
 {
@@ -94,7 +121,7 @@ __device__ __forceinline__ void compact_chunk(const Params<R> &p, int ts, int64_
                 p.ob_pos[(ob * D) + d * p.ob_cap + slot] = x2[d] - R(delta[d] * p.T[d]);
 #pragma unroll
             for (int m = 0; m < 3; ++m) p.ob_u[(ob * 3) + m * p.ob_cap + slot] = u[m];
-            p.ob_dir[ob + slot] = code;
+            p.ob_dir[(int64_t)ts * p.ob_dir_stride + slot] = code;
         } else {
             latch(p.err, ERR_CAPACITY);
         }
@@ -109,8 +136,13 @@ __device__ __forceinline__ void compact_chunk(const Params<R> &p, int ts, int64_
 // The current block is accumulated in LDS in type A (FP64 by default: the
 // LDS FP64 atomic add sustains a far higher rate on gfx950 than the FP32
 // one under the many-address pattern of the deposit, and sums more
-// accurately); it is rounded to R once, at the flush.
-template <typename R, int D, bool FUSED, typename A>
+// accurately); it is rounded to R once, at the flush.  With HALFB the
+// kernel applies push_half_b1 to its LDS copy of B itself (global B stays
+// at B^{n-1/2}).  Each thread takes U particles per group (element
+// c0 + j*blockDim + t), so every load and store instruction stays
+// coalesced while U loads per array are in flight; the stable compaction
+// runs once per group.
+template <typename R, int D, bool FUSED, bool HALFB, typename A, int U>
 __global__ void __launch_bounds__(1024) k_push(Params<R> p)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -119,70 +151,172 @@ __global__ void __launch_bounds__(1024) k_push(Params<R> p)
     const FieldBox<D> fb(p.T);
     const CurBox<D> cb(p.T);
     A *sJ = reinterpret_cast<A *>(smem);
-    R *sF = reinterpret_cast<R *>(sJ + (FUSED ? 3 * cb.n : 0));
-    int *sTot = reinterpret_cast<int *>(sF + 6 * fb.n);
-    stage_fields<R, D>(p, td, sF, fb);
+    R *sE = reinterpret_cast<R *>(sJ + (FUSED ? 3 * cb.n : 0));
+    R *sB = sE + 3 * cb.n;
+    int *sTot = reinterpret_cast<int *>(sB + 3 * fb.n);
+    stage_block<R, D>(p.E, p.cells_total, td, p.T, sE, cb);
+    stage_block<R, D>(p.B, p.cells_total, td, p.T, sB, fb);
     if constexpr (FUSED) {
         for (int k = threadIdx.x; k < 3 * cb.n; k += blockDim.x) sJ[k] = A(0);
     }
     __syncthreads();
-    const R c = p.c;
+    if constexpr (HALFB) {
+        half_b_lds<R, D>(sB, fb, sE, cb, R(0.5) * p.c);
+        __syncthreads();
+    }
+    const R c = p.c, inv_c = p.inv_c;
     const int64_t cap = p.cap_total;
+    const int G = U * blockDim.x;
     int parity = 0;
+    int32_t errs = 0;
     for (int s = 0; s < p.nspecies; ++s) {
         const int ts = t * p.nspecies + s;
         const int64_t so = p.seg_off[ts];
         const int cnt = p.seg_cnt[ts];
         const R q = p.charge[td.box * p.nspecies + s];
         const R sq = p.qm[td.box * p.nspecies + s];
+        // uniform per-species base pointers, 32-bit particle indices
+        R *X[3], *V[3], *XO[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            X[d] = p.pos + (d < D ? d : 0) * cap + so;
+            XO[d] = p.xold + (d < D ? d : 0) * cap + so;
+            V[d] = p.u + d * cap + so;
+        }
         int keep = 0, nleave = 0;
-        for (int c0 = 0; c0 < cnt; c0 += blockDim.x) {
-            const int i = c0 + threadIdx.x;
-            bool valid = i < cnt;
-            R x[3] = {0, 0, 0}, u[3] = {0, 0, 0}, x2[3] = {0, 0, 0}, dv[3] = {0, 0, 0};
-            int delta[3] = {0, 0, 0};
-            int code = centre_code<D>();
-            if (valid) {
+        // next group's particles, loaded one group ahead.  Segment
+        // capacities are multiples of the group size, so every lane of a
+        // group indexes a slot of the segment (lanes past the count read
+        // and write free slots): loads and stores need no branch.
+        R nx[U][3], nu[U][3];
 #pragma unroll
-                for (int d = 0; d < D; ++d) x[d] = p.pos[d * cap + so + i];
+        for (int j = 0; j < U; ++j) {
 #pragma unroll
-                for (int m = 0; m < 3; ++m) u[m] = p.u[m * cap + so + i];
-                if (inside_tile<R, D>(x, p.T)) {
-                    R e[3], b[3];
-                    interp_all<R, D>(sF, fb, x, p.T, e, b);
-                    boris<R>(u, e, b, c, sq);
-                    displacement<R>(u, c, dv);
-                    bool ok = finite3<R>(u);
+            for (int d = 0; d < 3; ++d) nx[j][d] = nu[j][d] = R(0);
+            if (cnt > 0) {
+                const int i = j * (int)blockDim.x + (int)threadIdx.x;
 #pragma unroll
-                    for (int d = 0; d < D; ++d) x2[d] = x[d] + dv[d];
-                    ok = ok && moved_ok<R, D>(x2, dv, p.T);
-                    if (ok) {
+                for (int d = 0; d < D; ++d) nx[j][d] = X[d][i];
+#pragma unroll
+                for (int m = 0; m < 3; ++m) nu[j][m] = V[m][i];
+            }
+        }
+        for (int c0 = 0; c0 < cnt; c0 += G) {
+            R x[U][3], u[U][3], x2[U][3];
+            bool valid[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                valid[j] = c0 + j * (int)blockDim.x + (int)threadIdx.x < cnt;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    x[j][d] = nx[j][d];
+                    u[j][d] = nu[j][d];
+                    x2[j][d] = x[j][d];
+                }
+            }
+            // prefetch: the next group lies beyond every element this group
+            // writes (compaction only moves elements down)
+            if (c0 + G < cnt) {
+#pragma unroll
+                for (int j = 0; j < U; ++j) {
+                    const int i = c0 + G + j * (int)blockDim.x + (int)threadIdx.x;
+#pragma unroll
+                    for (int d = 0; d < D; ++d) nx[j][d] = X[d][i];
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) nu[j][m] = V[m][i];
+                }
+            }
+            int delta[U][3], code[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                delta[j][0] = delta[j][1] = delta[j][2] = 0;
+                code[j] = centre_code<D>();
+                if (!valid[j]) continue;
+                if (inside_tile<R, D>(x[j], p.T)) {
+                    R e[3], b[3], dv[3];
+                    interp_all<R, D>(sE, cb, sB, fb, x[j], p.T, e, b);
+                    boris<R>(u[j], e, b, c, inv_c, sq);
+                    displacement<R>(u[j], c, dv);
+#pragma unroll
+                    for (int d = 0; d < D; ++d) x2[j][d] = x[j][d] + dv[d];
+                    if (finite3<R>(u[j]) && moved_ok<R, D>(x2[j], dv, p.T)) {
                         if constexpr (FUSED) {
-                            zigzag<R, D, A>(sJ, cb, p.T, x, x2, dv, q);
-                            code = direction_code<R, D>(x2, p.T, delta);
+                            zigzag<R, D, A>(sJ, cb, p.T, x[j], x2[j], dv, q);
+                            code[j] = direction_code<R, D>(x2[j], p.T, delta[j]);
                         }
                     } else {
-                        latch(p.err, finite3<R>(u) ? ERR_CFL : ERR_NONFINITE);
+                        errs |= finite3<R>(u[j]) ? ERR_CFL : ERR_NONFINITE;
 #pragma unroll
-                        for (int d = 0; d < D; ++d) x2[d] = x[d];
+                        for (int d = 0; d < D; ++d) x2[j][d] = x[j][d];
                     }
                 } else {
-                    latch(p.err, ERR_OUT_OF_TILE);
+                    errs |= ERR_OUT_OF_TILE;
 #pragma unroll
-                    for (int d = 0; d < D; ++d) x2[d] = x[d];
+                    for (int d = 0; d < D; ++d) x2[j][d] = x[j][d];
                 }
             }
             if constexpr (FUSED) {
-                const int nvalid = min((int)blockDim.x, cnt - c0);
-                compact_chunk<R, D>(p, ts, so, valid, code, delta, x2, u, nvalid, sTot, parity, keep, nleave);
-            } else if (valid) {
+                // stable compaction: stayers in place (every destination is at
+                // or below an element this group has already read), leavers to
+                // the outbox rebased by -delta T
+                bool stay[U];
+                int pre[U];
 #pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    p.xold[d * cap + so + i] = x[d];
-                    p.pos[d * cap + so + i] = x2[d];
+                for (int j = 0; j < U; ++j) stay[j] = valid[j] && code[j] == centre_code<D>();
+                const int tot = wg_scan_flags<U>(stay, sTot, parity, pre);
+                parity ^= 1;
+                const int64_t ob = (int64_t)ts * p.ob_cap;
+#pragma unroll
+                for (int j = 0; j < U; ++j) {
+                    // one store path for every lane: stayers to their compacted
+                    // slot, leavers to the outbox, lanes past the count back to
+                    // their own free slot; the destination planes are selected,
+                    // so the stores do not diverge
+                    const int lane_idx = j * (int)blockDim.x + (int)threadIdx.x;
+                    int64_t slot = nleave + (lane_idx - pre[j]);
+                    const bool leave = valid[j] && !stay[j];
+                    if (leave && slot >= p.ob_cap) {
+                        errs |= ERR_CAPACITY;     // state is invalid from here on
+                        slot = p.ob_cap - 1;
+                    }
+                    R *dx[3], *du[3];
+                    int64_t k;
+                    if (leave) {
+                        k = slot;
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            dx[d] = p.ob_pos + ob * D + (d < D ? d : 0) * p.ob_cap;
+                            du[d] = p.ob_u + ob * 3 + d * p.ob_cap;
+                        }
+                    } else {
+                        k = stay[j] ? keep + pre[j] : c0 + lane_idx;
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            dx[d] = X[d];
+                            du[d] = V[d];
+                        }
+                    }
+#pragma unroll
+                    for (int d = 0; d < D; ++d) dx[d][k] = x2[j][d] - R(delta[j][d] * p.T[d]);
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) du[m][k] = u[j][m];
+                    p.ob_dir[(int64_t)ts * p.ob_dir_stride + (leave ? slot : p.ob_cap + lane_idx)] = code[j];
                 }
+                const int nvalid = min(G, cnt - c0);
+                keep += tot;
+                nleave += nvalid - tot;
+            } else {
 #pragma unroll
-                for (int m = 0; m < 3; ++m) p.u[m * cap + so + i] = u[m];
+                for (int j = 0; j < U; ++j) {
+                    const int i = c0 + j * blockDim.x + threadIdx.x;   // own slot, free past the count
+#pragma unroll
+                    for (int d = 0; d < D; ++d) {
+                        XO[d][i] = x[j][d];
+                        X[d][i] = x2[j][d];
+                    }
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) V[m][i] = u[j][m];
+                }
             }
         }
         if constexpr (FUSED) {
@@ -192,6 +326,7 @@ __global__ void __launch_bounds__(1024) k_push(Params<R> p)
             }
         }
     }
+    latch_wave(p.err, errs);
     if constexpr (FUSED) {
         __syncthreads();
         R *blk = p.jblk + (int64_t)t * 3 * cb.n;
@@ -284,7 +419,9 @@ __global__ void __launch_bounds__(256) k_fold(Params<R> p)
 // ---------------------------------------------------------------- fields
 
 // PHASE 0: B -= h curl+ E.  PHASE 1: E += h curl- B.  PHASE 2: E -= J.
-// PHASE 3: E += h curl- B - J.   (Eqs. fdB/fdE, differences of App. B)
+// PHASE 3: E += h curl- B - J.  PHASE 4: B -= h curl+ E twice (both half
+// updates of Table 1 in one pass, same arithmetic as two PHASE 0 passes).
+// (Eqs. fdB/fdE with the differences of App. B.)
 template <typename R, int D, int PHASE>
 __global__ void __launch_bounds__(256) k_field(Params<R> p, R h)
 {
@@ -302,7 +439,7 @@ __global__ void __launch_bounds__(256) k_field(Params<R> p, R h)
             return td.cell0 + x + (int64_t)n0 * (y + (int64_t)n1 * z);
         };
         const int64_t g = at(gx, gy, gz);
-        if constexpr (PHASE == 0) {
+        if constexpr (PHASE == 0 || PHASE == 4) {
             const R *Ex = p.E, *Ey = p.E + N, *Ez = p.E + 2 * N;
             const int64_t ip = D > 0 ? at(gx + 1 == n0 ? 0 : gx + 1, gy, gz) : g;
             const int64_t jp = D > 1 ? at(gx, gy + 1 == n1 ? 0 : gy + 1, gz) : g;
@@ -311,9 +448,18 @@ __global__ void __launch_bounds__(256) k_field(Params<R> p, R h)
             const R cx = (Ez[jp] - ez) - (Ey[kp] - ey);
             const R cy = (Ex[kp] - ex) - (Ez[ip] - ez);
             const R cz = (Ey[ip] - ey) - (Ex[jp] - ex);
-            p.B[g] -= h * cx;
-            p.B[N + g] -= h * cy;
-            p.B[2 * N + g] -= h * cz;
+            R bx = p.B[g], by = p.B[N + g], bz = p.B[2 * N + g];
+            bx -= h * cx;
+            by -= h * cy;
+            bz -= h * cz;
+            if constexpr (PHASE == 4) {
+                bx -= h * cx;
+                by -= h * cy;
+                bz -= h * cz;
+            }
+            p.B[g] = bx;
+            p.B[N + g] = by;
+            p.B[2 * N + g] = bz;
         } else if constexpr (PHASE == 2) {
             p.E[g] -= p.J[g];
             p.E[N + g] -= p.J[N + g];
@@ -378,11 +524,15 @@ __global__ void __launch_bounds__(1024) k_migrate_out(Params<R> p)
 }
 
 // Receive incoming particles: append, per direction code in increasing
-// order, the neighbour outbox entries addressed to this tile.
+// order, the neighbour outbox entries addressed to this tile.  The entries
+// of all neighbours are walked as one index space (direction-major), so a
+// tile needs a few chunks instead of one dependent round per neighbour.
 template <typename R, int D>
 __global__ void __launch_bounds__(1024) k_migrate_in(Params<R> p)
 {
     __shared__ int sTot[2 * MAX_WAVES];
+    __shared__ int sOff[ncodes<D>() + 1];
+    __shared__ int sSrc[ncodes<D>()];
     const int t = blockIdx.x;
     const TileDesc td = p.tiles[t];
     const int64_t cap = p.cap_total;
@@ -392,42 +542,57 @@ __global__ void __launch_bounds__(1024) k_migrate_in(Params<R> p)
         const int64_t so = p.seg_off[ts];
         const int scap = p.seg_cap[ts];
         int cnt = p.seg_cnt[ts];
-        for (int code = 0; code < ncodes<D>(); ++code) {
-            if (code == centre_code<D>()) continue;
+        if ((int)threadIdx.x < ncodes<D>()) {
+            const int code = threadIdx.x;
             int nc[3] = {0, 0, 0}, rem = code;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 if (d < D) {
-                    int delta = rem % 3 - 1;
+                    const int delta = rem % 3 - 1;
                     rem /= 3;
                     nc[d] = wrapi(td.tc[d] - delta, td.nt[d]);
                 }
             }
-            const int sid = td.tile0 + nc[0] + td.nt[0] * (nc[1] + td.nt[1] * nc[2]);
-            const int sts = sid * p.nspecies + s;
-            const int m = (int)min((int64_t)p.ob_cnt[sts], p.ob_cap);
-            const int64_t ob = (int64_t)sts * p.ob_cap;
-            for (int c0 = 0; c0 < m; c0 += blockDim.x) {
-                const int k = c0 + threadIdx.x;
-                const bool take = k < m && p.ob_dir[ob + k] == code;
-                int tot;
-                int pre = wg_scan_flag(take, sTot, parity, tot);
-                parity ^= 1;
-                if (take) {
-                    const int dst = cnt + pre;
-                    if (dst < scap) {
-#pragma unroll
-                        for (int d = 0; d < D; ++d) p.pos[d * cap + so + dst] = p.ob_pos[ob * D + d * p.ob_cap + k];
-#pragma unroll
-                        for (int mm = 0; mm < 3; ++mm) p.u[mm * cap + so + dst] = p.ob_u[ob * 3 + mm * p.ob_cap + k];
-                    } else {
-                        latch(p.err, ERR_CAPACITY);
-                    }
-                }
-                cnt += tot;
+            const int sts = (td.tile0 + nc[0] + td.nt[0] * (nc[1] + td.nt[1] * nc[2])) * p.nspecies + s;
+            sSrc[code] = sts;
+            sOff[code + 1] = code == centre_code<D>() ? 0 : (int)min((int64_t)p.ob_cnt[sts], p.ob_cap);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            sOff[0] = 0;
+            for (int k = 0; k < ncodes<D>(); ++k) sOff[k + 1] += sOff[k];
+        }
+        __syncthreads();
+        const int total = sOff[ncodes<D>()];
+        for (int c0 = 0; c0 < total; c0 += blockDim.x) {
+            const int e = c0 + threadIdx.x;
+            bool take = false;
+            int code = 0;
+            int64_t src = 0;
+            if (e < total) {
+                while (sOff[code + 1] <= e) ++code;
+                src = (int64_t)sSrc[code] * p.ob_cap + (e - sOff[code]);
+                take = p.ob_dir[(int64_t)sSrc[code] * p.ob_dir_stride + (e - sOff[code])] == code;
             }
+            int tot;
+            const int pre = wg_scan_flag(take, sTot, parity, tot);
+            parity ^= 1;
+            if (take) {
+                const int dst = cnt + pre;
+                if (dst < scap) {
+                    const int64_t sts = src / p.ob_cap, k = src - sts * p.ob_cap;
+#pragma unroll
+                    for (int d = 0; d < D; ++d) p.pos[d * cap + so + dst] = p.ob_pos[sts * p.ob_cap * D + d * p.ob_cap + k];
+#pragma unroll
+                    for (int mm = 0; mm < 3; ++mm) p.u[mm * cap + so + dst] = p.ob_u[sts * p.ob_cap * 3 + mm * p.ob_cap + k];
+                } else {
+                    latch(p.err, ERR_CAPACITY);
+                }
+            }
+            cnt += tot;
         }
         if (threadIdx.x == 0) p.seg_cnt[ts] = min(cnt, scap);
+        __syncthreads();   // sOff / sSrc are rewritten for the next species
     }
 }
 

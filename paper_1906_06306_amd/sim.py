@@ -126,8 +126,9 @@ class PicSim:
     def fdtd(self, phase: int):
         L.check(L.lib().pic_fdtd_step(self.ctx, phase))
 
-    def push(self, fused: bool = True):
-        L.check(L.lib().pic_push_interp(self.ctx, L.PIC_FUSED if fused else 0))
+    def push(self, fused: bool = True, half_b: bool = False):
+        flags = (L.PIC_FUSED if fused else 0) | (L.PIC_PUSH_HALF_B if half_b else 0)
+        L.check(L.lib().pic_push_interp(self.ctx, flags))
 
     def deposit(self):
         L.check(L.lib().pic_deposit_current(self.ctx, 0))
@@ -135,8 +136,9 @@ class PicSim:
     def sort_migrate(self, sort_cells: bool = False):
         L.check(L.lib().pic_sort_migrate(self.ctx, L.PIC_SORT_CELLS if sort_cells else 0))
 
-    def step(self, n: int = 1, fused: bool = True, sort_cells: bool = False):
-        flags = (L.PIC_FUSED if fused else 0) | (L.PIC_SORT_CELLS if sort_cells else 0)
+    def step(self, n: int = 1, fused: bool = True, sort_cells: bool = False, half_b_in_push: bool = False):
+        flags = ((L.PIC_FUSED if fused else 0) | (L.PIC_SORT_CELLS if sort_cells else 0)
+                 | (L.PIC_PUSH_HALF_B if half_b_in_push else 0))
         fn = L.lib().pic_step
         for _ in range(n):
             L.check(fn(self.ctx, flags))

@@ -135,16 +135,18 @@ def test_unfused_step_stage_by_stage(D, n, T, ppc, prec):
     sim.close()
 
 
+@pytest.mark.parametrize("half_b_in_push", [False, True])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("D,n,T,ppc", CASES)
-def test_fused_step_matches_oracle_and_unfused(D, n, T, ppc, prec):
-    """One fused step (push + deposit + pack in one kernel) against the
-    oracle's full step, and its particle arrays against the unfused path."""
+def test_fused_step_matches_oracle_and_unfused(D, n, T, ppc, prec, half_b_in_push):
+    """One fused step (push + deposit + pack in one kernel, optionally with
+    push_half_b1 done inside the push) against the oracle's full step, and
+    its particle arrays against the unfused path."""
     plasma = synth.small_random(D, n, ppc, seed=21 + D, field_amp=0.05)
     sim = make_sim(plasma, T, prec)
     ref = make_sim(plasma, T, prec)
     st = common_state(sim, plasma)
-    sim.step(1, fused=True)
+    sim.step(1, fused=True, half_b_in_push=half_b_in_push)
     ref.step(1, fused=False)
     st.step(1)
     tol = TOL[prec]
@@ -230,7 +232,9 @@ def test_capacity_overflow_is_reported():
     (forced from the host with a tiny capacity; no kernel goes out of
     bounds)."""
     from paper_1906_06306_amd import _lib as L
-    plasma = synth.small_random(2, (32, 32), 4, seed=1)
+    # 16 particles per cell per species: 1024 per 8x8 tile, against segments
+    # of 256 (the requested 64 rounded up to the push kernel's group)
+    plasma = synth.small_random(2, (32, 32), 16, seed=1)
     nt = 4 * 4
     cap = np.full((nt, 2), 64, dtype=np.int64)
     with pytest.raises(L.PicError) as e:
