@@ -60,8 +60,9 @@ def test_query_layout(lib):
     assert code == 0
     assert lay.cells_total == 64 * 64 and lay.tiles_total == 16
     assert lay.elem_bytes == 4
-    # capacity: ceil(1.25 * 1024) + 64 rounded to 64, per tile and species
-    per = -(-int(np.ceil(1.25 * 1024) + 64) // 64) * 64
+    # capacity: ceil(1.25 * 1024) + 64 rounded up to the push group of
+    # 256 threads x 1 particle, per tile and species
+    per = -(-int(np.ceil(1.25 * 1024) + 64) // 256) * 256
     assert lay.capacity_total == per * 16 * 2
     offs = [lay.off_E, lay.off_B, lay.off_J, lay.off_pos, lay.off_u, lay.off_xold, lay.off_seg_offset,
             lay.off_seg_capacity, lay.off_seg_count, lay.off_error, lay.off_flags]
