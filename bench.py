@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=1024, help="cells per side")
     ap.add_argument("--ppc", type=int, default=16, help="particles per cell per species")
-    ap.add_argument("--tile", type=int, default=32)
+    ap.add_argument("--tile", default="auto", help="tile edge, or 'auto' (autotuner over 8/16/32)")
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -51,6 +51,9 @@ def parse():
                     help="precision of the --profile-steps run")
     ap.add_argument("--capacity", type=float, default=2.0,
                     help="tile segment capacity over the mean count (turbulent compression)")
+    ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps timed for the CPU baseline")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (to scale rocprofv3 FETCH/WRITE_SIZE)")
     return ap.parse_args()
 
 
@@ -67,12 +70,12 @@ def push_bytes(D, w, n_particles, n_cells):
     return n_particles * 2 * (D + 3) * w + n_cells * 9 * w
 
 
-def run_gpu(plasma, args, precision, steps, warmup, profile_only=False):
+def run_gpu(plasma, args, precision, steps, warmup, tile, profile_only=False):
     import torch
     from paper_1906_06306_amd import _lib as L
     from paper_1906_06306_amd.sim import PicSim
 
-    sim = PicSim(plasma, tile=(args.tile, args.tile), precision=precision, block=args.block,
+    sim = PicSim(plasma, tile=(tile, tile), precision=precision, block=args.block,
                  capacity_factor=args.capacity)
     stream = torch.cuda.current_stream()
     lib = L.lib()
@@ -117,14 +120,36 @@ def run_gpu(plasma, args, precision, steps, warmup, profile_only=False):
     return dict(seconds=dt, push_ms=push_ms, diag=diag)
 
 
-def cpu_oracle_rate(plasma):
-    """The FP64 oracle, as it stands, on one full step of the same workload."""
+def cpu_oracle_rate(plasma, steps):
+    """The FP64 oracle, as it stands, on full steps of the same workload."""
     import oracle
     st = oracle.State(plasma)
     t0 = time.perf_counter()
-    st.step(1)
+    st.step(steps)
     dt = time.perf_counter() - t0
-    return plasma.nparticles / dt, dt
+    return plasma.nparticles * steps / dt, dt
+
+
+def pick_tile(plasma, args, precision):
+    if args.tile != "auto":
+        return int(args.tile), None
+    from paper_1906_06306_amd import autotune
+    (T, _), res = autotune.tune(plasma, precision, blocks=(args.block,), capacity_factor=args.capacity, log=log)
+    return T, {f"T{k[0]}_b{k[1]}": round(v * 1e3, 4) for k, v in res.items()}
+
+
+def calibrate_copy():
+    """A plain device copy of 1 GiB (read 1 GiB, write 1 GiB): the reference
+    that scales rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log("copy calibration: 3 copies of 1 GiB done")
 
 
 def main():
@@ -137,26 +162,32 @@ def main():
     import synth
 
     assert torch.cuda.is_available(), "no GPU"
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     t0 = time.perf_counter()
     plasma = synth.turbulence(n=args.n, ppc=args.ppc)
     log(f"generated {plasma.nparticles} particles on {args.n}^2 cells in {time.perf_counter() - t0:.1f}s")
     n_p, n_c, D = plasma.nparticles, plasma.ncells, plasma.D
     if args.profile_steps:
-        code = run_gpu(plasma, args, args.precision, args.profile_steps, 0, profile_only=True)
+        tile = 16 if args.tile == "auto" else int(args.tile)
+        code = run_gpu(plasma, args, args.precision, args.profile_steps, 0, tile, profile_only=True)
         log(f"profile run done, device status {code}")
         return
-    log("fp32 run")
-    r32 = run_gpu(plasma, args, "fp32", args.steps, args.warmup)
+    tile32, tune32 = pick_tile(plasma, args, "fp32")
+    log(f"fp32 run, tile {tile32}")
+    r32 = run_gpu(plasma, args, "fp32", args.steps, args.warmup, tile32)
     r64 = None
     if not args.no_fp64:
-        log("fp64 run")
-        r64 = run_gpu(plasma, args, "fp64", args.steps, args.warmup)
+        tile64, tune64 = pick_tile(plasma, args, "fp64")
+        log(f"fp64 run, tile {tile64}")
+        r64 = run_gpu(plasma, args, "fp64", args.steps, args.warmup, tile64)
     cpu = None
     if not args.no_cpu:
-        log("cpu oracle: one full step")
-        rate, sec = cpu_oracle_rate(plasma)
+        log(f"cpu oracle: {args.cpu_steps} full steps")
+        rate, sec = cpu_oracle_rate(plasma, args.cpu_steps)
         cpu = {"value": rate, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-               "sample": f"1 full step of the same {args.n}^2 workload ({n_p} particles), "
+               "sample": f"{args.cpu_steps} full steps of the same {args.n}^2 workload ({n_p} particles), "
                          f"single-threaded FP64 C oracle, {sec:.1f} s"}
     value = n_p * args.steps / r32["seconds"]
     pb = push_bytes(D, 4, n_p, n_c)
@@ -175,9 +206,10 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"2D3V decaying turbulence {args.n}x{args.n} periodic, "
-                               f"{args.tile}x{args.tile} tiles, {args.ppc} ppc/species pair plasma, "
+                               f"{args.ppc} ppc/species pair plasma, "
                                "theta=0.3, sigma=10, dB/B0=1 (64 modes), c/w_p=3 cells, Courant 0.45",
-                   "particles": n_p, "cells": n_c, "block": args.block},
+                   "particles": n_p, "cells": n_c, "tile": tile32, "block": args.block,
+                   "autotune_ms_per_step": tune32},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_push<float,2,fused>", "push_ms": r32["push_ms"],
@@ -191,7 +223,8 @@ def main():
         v64 = n_p * args.steps / r64["seconds"]
         out["fp64"] = {"value": v64, "ms_per_step": r64["seconds"] / args.steps * 1e3,
                        "push_ms": r64["push_ms"], "speedup_fp32_over_fp64": value / v64,
-                       "gauss_max": r64["diag"]["gauss_max"]}
+                       "tile": tile64, "autotune_ms_per_step": tune64,
+                       "gauss_max": r64["diag"]["gauss_max"], "status": r64["diag"]["status"]}
     print(json.dumps(out), flush=True)
 
 
