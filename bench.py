@@ -49,7 +49,7 @@ def parse():
                     help="only run this many fused steps (for rocprofv3), no JSON")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"],
                     help="precision of the --profile-steps run")
-    ap.add_argument("--capacity", type=float, default=2.0,
+    ap.add_argument("--capacity", type=float, default=3.0,
                     help="tile segment capacity over the mean count (turbulent compression)")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps timed for the CPU baseline")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -189,6 +189,9 @@ def main():
         cpu = {"value": rate, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
                "sample": f"{args.cpu_steps} full steps of the same {args.n}^2 workload ({n_p} particles), "
                          f"single-threaded FP64 C oracle, {sec:.1f} s"}
+    if r32["diag"]["status"] != 0:
+        log(f"WARNING: device status {r32['diag']['status']} after the FP32 run (capacity or "
+            "numerical error): the measurement is invalid; raise --capacity")
     value = n_p * args.steps / r32["seconds"]
     pb = push_bytes(D, 4, n_p, n_c)
     achieved = pb / (r32["push_ms"] * 1e-3) / 1e9
