@@ -122,6 +122,11 @@ typedef struct {
  * working precision instead of FP64 (the default; the block is rounded to
  * the working precision once when it is written out). */
 #define PIC_OPT_ACC_WORKING 1u
+/* pic_config.options: run the push as a persistent tile walker (a grid of
+ * resident work-groups pulls tiles, heaviest first, from an atomic counter)
+ * instead of one work-group per tile; for uneven tile loads and batches of
+ * boxes of different sizes. */
+#define PIC_OPT_PERSISTENT 2u
 
 /* Byte offsets of the regions inside the caller's workspace.  Fields:
  * [3][cells_total] each, boxes concatenated (box b starts at cell offset
@@ -222,6 +227,15 @@ pic_status pic_sort_migrate(pic_ctx *ctx, uint32_t flags);
 /* One full time step in Table-1 order (see the top of this header);
  * flags as for pic_push_interp, plus PIC_SORT_CELLS. */
 pic_status pic_step(pic_ctx *ctx, uint32_t flags);
+
+/* Capture nsteps calls of pic_step(flags) into a HIP graph on the context's
+ * stream (after one eager step, which also sets kernel attributes).  The
+ * steps contain no memset nodes (fills are kernels).  Replaces a previous
+ * graph.  PIC_E_STATE if called between a push and its migration. */
+pic_status pic_graph_capture(pic_ctx *ctx, int32_t nsteps, uint32_t flags);
+
+/* Replay the captured steps on the context's stream. */
+pic_status pic_graph_launch(pic_ctx *ctx);
 
 /* Synchronise the stream and return (then clear) the latched device error
  * bits, or PIC_E_HIP. */

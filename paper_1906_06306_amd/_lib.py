@@ -27,9 +27,11 @@ PIC_FUSED = 1
 PIC_SORT_CELLS = 2
 PIC_PUSH_HALF_B = 4
 PIC_OPT_ACC_WORKING = 1
+PIC_OPT_PERSISTENT = 2
 
 EXPORTS = ["pic_query", "pic_init_tiles", "pic_fdtd_step", "pic_push_interp", "pic_deposit_current",
-           "pic_sort_migrate", "pic_step", "pic_error", "pic_diagnostics", "pic_destroy", "pic_last_error"]
+           "pic_sort_migrate", "pic_step", "pic_graph_capture", "pic_graph_launch", "pic_error",
+           "pic_diagnostics", "pic_destroy", "pic_last_error"]
 
 P = ctypes.c_void_p
 I32 = ctypes.c_int32
@@ -93,6 +95,8 @@ def lib():
             "pic_deposit_current": [P, U32],
             "pic_sort_migrate": [P, U32],
             "pic_step": [P, U32],
+            "pic_graph_capture": [P, I32, U32],
+            "pic_graph_launch": [P],
             "pic_error": [P],
             "pic_diagnostics": [P, P],
             "pic_destroy": [P],

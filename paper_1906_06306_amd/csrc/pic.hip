@@ -229,6 +229,10 @@ pic_status make_layout(const pic_config *c, const int64_t *counts, Layout &L)
 struct pic_ctx {
     int D, prec, ns, nb, block;
     bool acc_working;   // LDS current block in the working precision
+    bool persistent;    // push as a persistent tile walker
+    int n_cu;           // compute units of the device
+    hipGraphExec_t graph;   // captured steps, or null
+    int graph_steps;
     int T[3];
     double c;
     Layout L;
@@ -335,10 +339,24 @@ struct Impl {
     {
         Params<R> p = params<R>(x);
         size_t lds = push_lds(x, FUSED, sizeof(A));
-        dim3 g((unsigned)x->L.pub.tiles_total), b(x->block);
-        pic_status st = set_lds(pic::k_push<R, D, FUSED, HALFB, A, PUSH_UNROLL>, lds);
-        if (st) return st;
-        hipLaunchKernelGGL((pic::k_push<R, D, FUSED, HALFB, A, PUSH_UNROLL>), g, b, lds, x->stream, p);
+        dim3 b(x->block);
+        if (x->persistent) {
+            auto kern = pic::k_push_persistent<R, D, FUSED, HALFB, A, PUSH_UNROLL>;
+            pic_status st = set_lds(kern, lds);
+            if (st) return st;
+            int per_cu = 0;
+            HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kern),
+                                                                x->block, lds));
+            const int64_t grid = std::min<int64_t>(x->L.pub.tiles_total, (int64_t)std::max(per_cu, 1) * x->n_cu);
+            st = fill<int32_t>(x, p.queue, 1, 0);
+            if (st) return st;
+            hipLaunchKernelGGL(kern, dim3((unsigned)grid), b, lds, x->stream, p);
+        } else {
+            auto kern = pic::k_push<R, D, FUSED, HALFB, A, PUSH_UNROLL>;
+            pic_status st = set_lds(kern, lds);
+            if (st) return st;
+            hipLaunchKernelGGL(kern, dim3((unsigned)x->L.pub.tiles_total), b, lds, x->stream, p);
+        }
         HIP_OK(hipGetLastError());
         return PIC_OK;
     }
@@ -593,6 +611,18 @@ pic_status pic_init_tiles(const pic_config *cfg, const int64_t *counts, void *wo
     x->nb = cfg->n_boxes;
     x->block = cfg->block ? cfg->block : 256;
     x->acc_working = (cfg->options & PIC_OPT_ACC_WORKING) != 0;
+    x->persistent = (cfg->options & PIC_OPT_PERSISTENT) != 0;
+    x->graph = nullptr;
+    x->graph_steps = 0;
+    {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+            delete x;
+            return fail(PIC_E_HIP, "cannot query the device");
+        }
+        x->n_cu = prop.multiProcessorCount;
+    }
     for (int d = 0; d < 3; ++d) x->T[d] = cfg->tile[d];
     x->c = cfg->cfl;
     x->stream = reinterpret_cast<hipStream_t>(hip_stream);
@@ -693,6 +723,44 @@ pic_status pic_step(pic_ctx *x, uint32_t flags)
     return pic_sort_migrate(x, flags);
 }
 
+pic_status pic_graph_capture(pic_ctx *x, int32_t nsteps, uint32_t flags)
+{
+    if (!x || nsteps < 1) return fail(PIC_E_ARG, "need a context and nsteps >= 1");
+    if (x->state != 0) return fail(PIC_E_STATE, "capture must start between steps");
+    if (x->graph) {
+        HIP_OK(hipGraphExecDestroy(x->graph));
+        x->graph = nullptr;
+    }
+    // one eager step sets the kernels' LDS attributes before capture
+    pic_status st = pic_step(x, flags);
+    if (st) return st;
+    HIP_OK(hipStreamSynchronize(x->stream));
+    HIP_OK(hipStreamBeginCapture(x->stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < nsteps && !st; ++k) st = pic_step(x, flags);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(x->stream, &g);
+    if (st) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(PIC_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&x->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        x->graph = nullptr;
+        return fail(PIC_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    x->graph_steps = nsteps;
+    return PIC_OK;
+}
+
+pic_status pic_graph_launch(pic_ctx *x)
+{
+    if (!x || !x->graph) return fail(PIC_E_STATE, "no captured graph");
+    HIP_OK(hipGraphLaunch(x->graph, x->stream));
+    return PIC_OK;
+}
+
 pic_status pic_error(pic_ctx *x)
 {
     if (!x) return fail(PIC_E_ARG, "null context");
@@ -715,6 +783,7 @@ pic_status pic_diagnostics(pic_ctx *x, pic_diag *out)
 
 pic_status pic_destroy(pic_ctx *x)
 {
+    if (x && x->graph) (void)hipGraphExecDestroy(x->graph);
     delete x;
     return PIC_OK;
 }

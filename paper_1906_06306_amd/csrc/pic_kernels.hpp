@@ -143,10 +143,8 @@ __device__ __forceinline__ void compact_chunk(const Params<R> &p, int ts, int64_
 // coalesced while U loads per array are in flight; the stable compaction
 // runs once per group.
 template <typename R, int D, bool FUSED, bool HALFB, typename A, int U>
-__global__ void __launch_bounds__(1024) k_push(Params<R> p)
+__device__ __forceinline__ void push_tile(const Params<R> &p, const int t, unsigned char *smem)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int t = p.order ? p.order[blockIdx.x] : (int)blockIdx.x;
     const TileDesc td = p.tiles[t];
     const FieldBox<D> fb(p.T);
     const CurBox<D> cb(p.T);
@@ -331,6 +329,33 @@ __global__ void __launch_bounds__(1024) k_push(Params<R> p)
         __syncthreads();
         R *blk = p.jblk + (int64_t)t * 3 * cb.n;
         for (int k = threadIdx.x; k < 3 * cb.n; k += blockDim.x) blk[k] = (R)sJ[k];
+    }
+}
+
+// One work-group per tile, tiles dispatched heaviest first.
+template <typename R, int D, bool FUSED, bool HALFB, typename A, int U>
+__global__ void __launch_bounds__(1024) k_push(Params<R> p)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    push_tile<R, D, FUSED, HALFB, A, U>(p, p.order[blockIdx.x], smem);
+}
+
+// Persistent tile walker: a grid sized to the resident work-groups pulls
+// tiles (heaviest first) from an atomic counter until every tile is taken;
+// every work-group leaves the loop when the counter passes the tile count.
+template <typename R, int D, bool FUSED, bool HALFB, typename A, int U>
+__global__ void __launch_bounds__(1024) k_push_persistent(Params<R> p)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(p.queue, 1);
+        __syncthreads();
+        const int k = next;
+        __syncthreads();
+        if (k >= p.ntiles) break;
+        push_tile<R, D, FUSED, HALFB, A, U>(p, p.order[k], smem);
+        __syncthreads();
     }
 }
 

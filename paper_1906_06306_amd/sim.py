@@ -37,7 +37,8 @@ class PicSim:
     """A batch of periodic boxes stepped together on one GPU."""
 
     def __init__(self, boxes, tile, precision: str = "fp32", block: int = 256, capacity_factor: float = 1.25,
-                 tile_capacity=None, outbox_capacity: int = 0, options: int = 0, device: str = "cuda:0"):
+                 tile_capacity=None, outbox_capacity: int = 0, options: int = 0, device: str = "cuda:0",
+                 stream=None):
         if not isinstance(boxes, (list, tuple)):
             boxes = [boxes]
         boxes = [b if isinstance(b, Box) else box_from_plasma(b) for b in boxes]
@@ -110,7 +111,7 @@ class PicSim:
         init = L.PicInitData(self._counts.ctypes.data, ctypes.cast(self._pos_arr, ctypes.c_void_p),
                              ctypes.cast(self._u_arr, ctypes.c_void_p), ctypes.cast(self._e_arr, ctypes.c_void_p),
                              ctypes.cast(self._b_arr, ctypes.c_void_p))
-        self.stream = torch.cuda.current_stream(self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         ctx = ctypes.c_void_p()
         L.check(lib.pic_init_tiles(ctypes.byref(cfg), self._counts.ctypes.data, ctypes.c_void_p(self.ws_ptr),
                                    int(lay.total_bytes), ctypes.byref(init), ctypes.c_void_p(self.stream.cuda_stream),
@@ -142,6 +143,18 @@ class PicSim:
         fn = L.lib().pic_step
         for _ in range(n):
             L.check(fn(self.ctx, flags))
+
+    def capture(self, nsteps: int = 1, fused: bool = True, sort_cells: bool = False,
+                half_b_in_push: bool = True):
+        """Capture nsteps steps into a HIP graph (after one eager step)."""
+        flags = ((L.PIC_FUSED if fused else 0) | (L.PIC_SORT_CELLS if sort_cells else 0)
+                 | (L.PIC_PUSH_HALF_B if half_b_in_push else 0))
+        L.check(L.lib().pic_graph_capture(self.ctx, nsteps, flags))
+
+    def replay(self, n: int = 1):
+        fn = L.lib().pic_graph_launch
+        for _ in range(n):
+            L.check(fn(self.ctx))
 
     def error(self) -> int:
         code = L.lib().pic_error(self.ctx)
