@@ -59,6 +59,7 @@ def lib():
             "orc_div_face": (None, [P, P, P]),
             "orc_field_energy": (Dbl, [P, P, P]),
             "orc_kinetic_energy": (Dbl, [I64, Dbl, Dbl, P]),
+            "orc_step_adjoint": (I, [I, P, Dbl, I, P, P, P, P, P, P, P, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -201,6 +202,34 @@ class State:
             if rc != 0:
                 raise MemoryError("oracle step could not allocate scratch")
 
+    def copy(self):
+        other = State.__new__(State)
+        other.D, other.n, other.c = self.D, self.n, self.c
+        other.E, other.B, other.J = self.E.copy(), self.B.copy(), self.J.copy()
+        other.x = [x.copy() for x in self.x]
+        other.u = [u.copy() for u in self.u]
+        other.q, other.s, other.m = list(self.q), list(self.s), list(self.m)
+        return other
+
+    def step_adjoint(self, lx, lu, lE, lB):
+        """Reverse one step taken from this state: lx, lu (per species) and
+        lE, lB (fields) hold the adjoints of the step's outputs on entry and
+        the adjoints of this state on exit (all modified in place)."""
+        ns = len(self.x)
+        dims = _dims(self.n)
+        n_per = np.array([x.shape[1] for x in self.x], dtype=np.int64)
+        arr = lambda lst: (ctypes.c_void_p * ns)(*[a.ctypes.data for a in lst])
+        xp, up, lxp, lup = arr(self.x), arr(self.u), arr(lx), arr(lu)
+        q = np.array(self.q, dtype=np.float64)
+        s = np.array(self.s, dtype=np.float64)
+        rc = lib().orc_step_adjoint(self.D, _p(dims), self.c, ns, _p(n_per),
+                                    ctypes.cast(xp, ctypes.c_void_p), ctypes.cast(up, ctypes.c_void_p),
+                                    _p(q), _p(s), _p(self.E), _p(self.B),
+                                    ctypes.cast(lxp, ctypes.c_void_p), ctypes.cast(lup, ctypes.c_void_p),
+                                    _p(lE), _p(lB))
+        if rc != 0:
+            raise MemoryError("oracle adjoint could not allocate scratch")
+
     def rho(self):
         out = np.zeros(int(np.prod(_dims(self.n))))
         for x, q in zip(self.x, self.q):
@@ -217,3 +246,28 @@ class State:
         uf = field_energy(self.n, self.E, self.B)
         uk = sum(kinetic_energy(m, self.c, u) for m, u in zip(self.m, self.u))
         return uf, uk
+
+
+def loss_e2(st) -> float:
+    """L = sum over cells of |E|^2."""
+    return float(np.sum(st.E * st.E))
+
+
+def adjoint_run(st0, nsteps: int):
+    """Loss sum |E^N|^2 after nsteps from state st0 (not modified) and its
+    adjoints with respect to st0: returns (L, lx, lu, lE, lB).  Keeps every
+    intermediate state (for small systems)."""
+    states = [st0.copy()]
+    for _ in range(nsteps):
+        nxt = states[-1].copy()
+        nxt.step(1)
+        states.append(nxt)
+    fin = states[-1]
+    L = loss_e2(fin)
+    lE = 2.0 * fin.E.copy()
+    lB = np.zeros_like(fin.B)
+    lx = [np.zeros_like(x) for x in fin.x]
+    lu = [np.zeros_like(u) for u in fin.u]
+    for k in range(nsteps - 1, -1, -1):
+        states[k].step_adjoint(lx, lu, lE, lB)
+    return L, lx, lu, lE, lB

@@ -406,3 +406,322 @@ double orc_kinetic_energy(int64_t np, double mass, double c, const double *u)
     }
     return mass * c * c * s;
 }
+
+/* ====================================================================== */
+/* Adjoint (reverse mode) of one full step, written by hand from the
+ * forward routines above.  Differentiation of the step is not in the paper;
+ * these routines are the exact vector-Jacobian products of orc_step (the
+ * piecewise definitions - floor, the relay point min/max, the CIC weights -
+ * are differentiated on the branch the forward value takes).            */
+
+/* Interpolation adjoint at one particle: adds w * lF into the field adjoint
+ * lFld of component comp at the 2^D points, and returns dF/dx_d (gradient
+ * of the interpolated value with respect to the particle position).      */
+static double interp_one(int D, const int n[3], const double *F, int comp, const double *xp,
+                         double *lFld, double lval, double grad[3])
+{
+    int64_t base[3] = {0, 0, 0};
+    double w[3] = {0.0, 0.0, 0.0};
+    for (int d = 0; d < D; ++d) {
+        double xi = xp[d] - stagger(comp, d);
+        double fl = floor(xi);
+        base[d] = (int64_t)fl;
+        w[d] = xi - fl;
+    }
+    double val = 0.0;
+    for (int d = 0; d < 3; ++d) grad[d] = 0.0;
+    for (int cn = 0; cn < (1 << D); ++cn) {
+        int64_t idx[3] = {base[0], base[1], base[2]};
+        double wt = 1.0;
+        for (int d = 0; d < D; ++d) {
+            int bit = (cn >> d) & 1;
+            idx[d] += bit;
+            wt *= bit ? w[d] : 1.0 - w[d];
+        }
+        int64_t c = cell(n, idx[0], idx[1], idx[2]);
+        val += wt * F[c];
+        if (lFld) lFld[c] += wt * lval;
+        for (int d = 0; d < D; ++d) {
+            double g = (cn >> d) & 1 ? 1.0 : -1.0;   /* d(weight factor)/dx_d */
+            for (int e = 0; e < D; ++e)
+                if (e != d) g *= ((cn >> e) & 1) ? w[e] : 1.0 - w[e];
+            grad[d] += g * F[c];
+        }
+    }
+    return val;
+}
+
+/* Boris adjoint: given u^{n-1/2} (u0), fields (Ep, Bp) and the adjoint lu1
+ * of u^{n+1/2}, returns the adjoints of u0, Ep, Bp.                       */
+static void boris_adjoint(double c, double s, const double u0[3], const double Ep[3], const double Bp[3],
+                          const double lu1[3], double lu0[3], double lE[3], double lB[3])
+{
+    double eps[3], a[3], t[3], w[3], b[3];
+    for (int i = 0; i < 3; ++i) {
+        eps[i] = 0.5 * s * Ep[i];
+        a[i] = c * u0[i] + eps[i];
+    }
+    double g1 = sqrt(1.0 + (a[0] * a[0] + a[1] * a[1] + a[2] * a[2]) / (c * c));
+    double kap = s / (2.0 * c * g1);
+    for (int i = 0; i < 3; ++i) t[i] = kap * Bp[i];
+    double tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+    double f = 2.0 / (1.0 + tt);
+    w[0] = a[0] + (a[1] * t[2] - a[2] * t[1]);
+    w[1] = a[1] + (a[2] * t[0] - a[0] * t[2]);
+    w[2] = a[2] + (a[0] * t[1] - a[1] * t[0]);
+    for (int i = 0; i < 3; ++i) b[i] = f * w[i];
+    /* forward: cc = a + b x t + eps, u1 = cc / c */
+    double lc[3], la[3], leps[3], lb[3], lt[3], lw[3];
+    for (int i = 0; i < 3; ++i) {
+        lc[i] = lu1[i] / c;
+        la[i] = lc[i];
+        leps[i] = lc[i];
+    }
+    /* b x t: d/db^T lc = t x lc ; d/dt^T lc = lc x b */
+    lb[0] = t[1] * lc[2] - t[2] * lc[1];
+    lb[1] = t[2] * lc[0] - t[0] * lc[2];
+    lb[2] = t[0] * lc[1] - t[1] * lc[0];
+    lt[0] = lc[1] * b[2] - lc[2] * b[1];
+    lt[1] = lc[2] * b[0] - lc[0] * b[2];
+    lt[2] = lc[0] * b[1] - lc[1] * b[0];
+    /* b = f w */
+    double lf = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        lw[i] = f * lb[i];
+        lf += w[i] * lb[i];
+    }
+    /* w = a + a x t: d/da^T lw = lw + t x lw ; d/dt^T lw = lw x a */
+    la[0] += lw[0] + (t[1] * lw[2] - t[2] * lw[1]);
+    la[1] += lw[1] + (t[2] * lw[0] - t[0] * lw[2]);
+    la[2] += lw[2] + (t[0] * lw[1] - t[1] * lw[0]);
+    lt[0] += lw[1] * a[2] - lw[2] * a[1];
+    lt[1] += lw[2] * a[0] - lw[0] * a[2];
+    lt[2] += lw[0] * a[1] - lw[1] * a[0];
+    /* f = 2/(1+|t|^2): df/dt = -f^2 t */
+    for (int i = 0; i < 3; ++i) lt[i] += -lf * f * f * t[i];
+    /* t = kap B */
+    double lkap = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        lB[i] = kap * lt[i];
+        lkap += Bp[i] * lt[i];
+    }
+    /* kap = s/(2 c g1): dkap/dg1 = -kap/g1 ; g1 = sqrt(1+|a|^2/c^2) */
+    double lg1 = -kap / g1 * lkap;
+    for (int i = 0; i < 3; ++i) la[i] += lg1 * a[i] / (c * c * g1);
+    /* a = c u0 + eps ; eps = s E / 2 */
+    for (int i = 0; i < 3; ++i) {
+        lu0[i] = c * la[i];
+        leps[i] += la[i];
+        lE[i] = 0.5 * s * leps[i];
+    }
+}
+
+/* One ZigZag segment: values and their derivatives.  For a segment with
+ * flux F, weights W, displacement dv (grid dims) in cell i, the value for
+ * component m at a corner is F_m * prod_a wf_a (+ F_m sa sb dv_a dv_b / 12
+ * with two transverse dims).  dF, dW, ddv hold d/d(input k) for the 2D+ng
+ * inputs k.  The adjoint sums lJ(point) * d(value)/d(input k) into lin[k]. */
+#define ZZ_NIN 6
+static void segment_adjoint(int D, const int n[3], const double *lJ, const double F[3],
+                            const double W[3], const double dv[3], const int64_t i[3],
+                            double dF[3][ZZ_NIN], double dW[3][ZZ_NIN], double ddv[3][ZZ_NIN], int nin,
+                            double *lin)
+{
+    int64_t N = ncells(n);
+    for (int m = 0; m < 3; ++m) {
+        int ntrans = 0;
+        for (int d = 0; d < D; ++d) ntrans += (d != m);
+        for (int cn = 0; cn < (1 << D); ++cn) {
+            if (m < D && ((cn >> m) & 1)) continue;
+            int64_t idx[3] = {i[0], i[1], i[2]};
+            double P = 1.0, C = 1.0;
+            for (int d = 0; d < D; ++d) {
+                if (d == m) continue;
+                int bit = (cn >> d) & 1;
+                idx[d] += bit;
+                P *= bit ? W[d] : 1.0 - W[d];
+                C *= bit ? dv[d] : -dv[d];
+            }
+            double lam = lJ[m * N + cell(n, idx[0], idx[1], idx[2])];
+            double wt = P + (ntrans == 2 ? C / 12.0 : 0.0);
+            for (int k = 0; k < nin; ++k) {
+                double dP = 0.0, dC = 0.0;
+                for (int d = 0; d < D; ++d) {
+                    if (d == m) continue;
+                    int bit = (cn >> d) & 1;
+                    double gP = bit ? dW[d][k] : -dW[d][k];
+                    double gC = bit ? ddv[d][k] : -ddv[d][k];
+                    double restP = 1.0, restC = 1.0;
+                    for (int e = 0; e < D; ++e) {
+                        if (e == m || e == d) continue;
+                        int be = (cn >> e) & 1;
+                        restP *= be ? W[e] : 1.0 - W[e];
+                        restC *= be ? dv[e] : -dv[e];
+                    }
+                    dP += gP * restP;
+                    dC += gC * restC;
+                }
+                double dwt = dP + (ntrans == 2 ? dC / 12.0 : 0.0);
+                lin[k] += lam * (dF[m][k] * wt + F[m] * dwt);
+            }
+        }
+    }
+}
+
+/* ZigZag adjoint of one particle moving x1 -> x2 with non-grid
+ * displacement disp[d >= D]: adds d(sum lJ . J)/d(x1, x2, disp_ng) into
+ * lx1[D], lx2[D], ldisp[3].                                             */
+static void zigzag_adjoint_one(int D, const int n[3], double q, const double *x1, const double *x2,
+                               const double disp[3], const double *lJ, double *lx1, double *lx2,
+                               double ldisp[3])
+{
+    /* inputs: k = d for x1_d, k = D + d for x2_d, k = 2D + (m - D) for disp_m (m >= D) */
+    int nin = 2 * D + (3 - D);
+    double F1[3], F2[3], W1[3] = {0, 0, 0}, W2[3] = {0, 0, 0}, d1[3] = {0, 0, 0}, d2[3] = {0, 0, 0};
+    double dF1[3][ZZ_NIN], dF2[3][ZZ_NIN], dW1[3][ZZ_NIN], dW2[3][ZZ_NIN], dd1[3][ZZ_NIN], dd2[3][ZZ_NIN];
+    memset(dF1, 0, sizeof dF1);
+    memset(dF2, 0, sizeof dF2);
+    memset(dW1, 0, sizeof dW1);
+    memset(dW2, 0, sizeof dW2);
+    memset(dd1, 0, sizeof dd1);
+    memset(dd2, 0, sizeof dd2);
+    int64_t i1[3] = {0, 0, 0}, i2[3] = {0, 0, 0};
+    for (int d = 0; d < 3; ++d) {
+        if (d < D) {
+            double a = x1[d], b = x2[d];
+            double fa = floor(a), fb = floor(b);
+            double lo = fa < fb ? fa : fb, hi = fa > fb ? fa : fb;
+            double mid = 0.5 * (a + b);
+            double inner = hi > mid ? hi : mid;
+            int mid_used = !(hi > mid);
+            double xr = (lo + 1.0) < inner ? (lo + 1.0) : inner;
+            if ((lo + 1.0) < inner) mid_used = 0;
+            double ra = mid_used ? 0.5 : 0.0, rb = ra;
+            int ka = d, kb = D + d;
+            F1[d] = q * (xr - a);
+            F2[d] = q * (b - xr);
+            W1[d] = 0.5 * (a + xr) - fa;
+            W2[d] = 0.5 * (b + xr) - fb;
+            d1[d] = xr - a;
+            d2[d] = b - xr;
+            dF1[d][ka] = q * (ra - 1.0);
+            dF1[d][kb] = q * rb;
+            dF2[d][ka] = -q * ra;
+            dF2[d][kb] = q * (1.0 - rb);
+            dW1[d][ka] = 0.5 * (1.0 + ra);
+            dW1[d][kb] = 0.5 * rb;
+            dW2[d][ka] = 0.5 * ra;
+            dW2[d][kb] = 0.5 * (1.0 + rb);
+            dd1[d][ka] = ra - 1.0;
+            dd1[d][kb] = rb;
+            dd2[d][ka] = -ra;
+            dd2[d][kb] = 1.0 - rb;
+            i1[d] = (int64_t)fa;
+            i2[d] = (int64_t)fb;
+        } else {
+            int k = 2 * D + (d - D);
+            F1[d] = F2[d] = q * 0.5 * disp[d];
+            dF1[d][k] = dF2[d][k] = 0.5 * q;
+        }
+    }
+    double lin[ZZ_NIN] = {0, 0, 0, 0, 0, 0};
+    segment_adjoint(D, n, lJ, F1, W1, d1, i1, dF1, dW1, dd1, nin, lin);
+    segment_adjoint(D, n, lJ, F2, W2, d2, i2, dF2, dW2, dd2, nin, lin);
+    for (int d = 0; d < D; ++d) {
+        lx1[d] += lin[d];
+        lx2[d] += lin[D + d];
+    }
+    for (int d = D; d < 3; ++d) ldisp[d] += lin[2 * D + (d - D)];
+}
+
+/* Adjoint of orc_step.  The state (x, u, E, B) at the start of the step is
+ * read only; on entry lx, lu, lE, lB hold the adjoints of the step's
+ * outputs (x^{n+1} before wrapping, u^{n+1/2}, E^{n+1}, B^{n+1/2}); on exit
+ * they hold the adjoints of its inputs (x^n, u^{n-1/2}, E^n, B^{n-1/2}).
+ * Wrapping x is a shift by a constant and does not change the adjoint.
+ * Returns 0, or -1 if scratch could not be allocated.                   */
+int orc_step_adjoint(int D, const int n[3], double c, int nspecies, const int64_t *n_per,
+                     double **x, double **u, const double *q, const double *sgn,
+                     const double *E, const double *B, double **lx, double **lu, double *lE, double *lB)
+{
+    int64_t N = ncells(n);
+    double h = 0.5 * c;
+    double *B1 = malloc(sizeof(double) * 3 * (size_t)N);
+    double *lJ = malloc(sizeof(double) * 3 * (size_t)N);
+    if (!B1 || !lJ) {
+        free(B1);
+        free(lJ);
+        return -1;
+    }
+    memcpy(B1, B, sizeof(double) * 3 * (size_t)N);
+    orc_advance_b(D, n, h, E, B1);                 /* B^n, used by the push */
+    /* add_cur: E^{n+1} = ... - J  ->  lJ = -lE */
+    for (int64_t k = 0; k < 3 * N; ++k) lJ[k] = -lE[k];
+    /* push_e: E^{n+1} = E + c curl- B^{n+1/2}  ->  lB += c curl+ lE */
+    orc_advance_b(D, n, -c, lE, lB);
+    /* push_half_b2: B^{n+1/2} = B^n - h curl+ E  ->  lE += -h curl- lB */
+    orc_advance_e(D, n, -h, lB, lE);
+    /* particles (interp_em, push, comp_curr) */
+    for (int s = 0; s < nspecies; ++s) {
+        int64_t np = n_per[s];
+        for (int64_t p = 0; p < np; ++p) {
+            double xp[3] = {0, 0, 0}, up[3], Ep[3], Bp[3], g[6][3];
+            for (int d = 0; d < D; ++d) xp[d] = x[s][d * np + p];
+            for (int i = 0; i < 3; ++i) up[i] = u[s][i * np + p];
+            for (int comp = 0; comp < 6; ++comp) {
+                double v = interp_one(D, n, comp < 3 ? E + comp * N : B1 + (comp - 3) * N, comp, xp, NULL, 0.0,
+                                      g[comp]);
+                if (comp < 3) Ep[comp] = v;
+                else Bp[comp - 3] = v;
+            }
+            /* forward push of this particle */
+            double u1[3] = {up[0], up[1], up[2]};
+            {
+                double Ea[3][1], Ba[3][1], uu[3][1];
+                for (int i = 0; i < 3; ++i) {
+                    Ea[i][0] = Ep[i];
+                    Ba[i][0] = Bp[i];
+                    uu[i][0] = u1[i];
+                }
+                orc_boris(1, c, sgn[s], &Ea[0][0], &Ba[0][0], &uu[0][0]);
+                for (int i = 0; i < 3; ++i) u1[i] = uu[i][0];
+            }
+            double gam = sqrt(1.0 + u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]);
+            double disp[3], x2[3] = {0, 0, 0};
+            for (int i = 0; i < 3; ++i) disp[i] = c * u1[i] / gam;
+            for (int d = 0; d < D; ++d) x2[d] = xp[d] + disp[d];
+            /* adjoint of the outputs of this particle */
+            double lx2[3] = {0, 0, 0}, lx1[3] = {0, 0, 0}, ldisp[3] = {0, 0, 0}, lu1[3];
+            for (int d = 0; d < D; ++d) lx2[d] = lx[s][d * np + p];
+            for (int i = 0; i < 3; ++i) lu1[i] = lu[s][i * np + p];
+            /* comp_curr */
+            zigzag_adjoint_one(D, n, q[s], xp, x2, disp, lJ, lx1, lx2, ldisp);
+            /* x2 = x1 + disp (grid dims) */
+            for (int d = 0; d < D; ++d) {
+                lx1[d] += lx2[d];
+                ldisp[d] += lx2[d];
+            }
+            /* disp = c u1 / gamma(u1) */
+            double ul = u1[0] * ldisp[0] + u1[1] * ldisp[1] + u1[2] * ldisp[2];
+            for (int i = 0; i < 3; ++i) lu1[i] += c * (ldisp[i] / gam - u1[i] * ul / (gam * gam * gam));
+            /* Boris */
+            double lu0[3], lEp[3], lBp[3];
+            boris_adjoint(c, sgn[s], up, Ep, Bp, lu1, lu0, lEp, lBp);
+            /* interpolation: scatter into the field adjoints, gradient in x */
+            for (int comp = 0; comp < 6; ++comp) {
+                double lval = comp < 3 ? lEp[comp] : lBp[comp - 3];
+                double gg[3];
+                interp_one(D, n, comp < 3 ? E + comp * N : B1 + (comp - 3) * N, comp, xp,
+                           comp < 3 ? lE + comp * N : lB + (comp - 3) * N, lval, gg);
+                for (int d = 0; d < D; ++d) lx1[d] += lval * gg[d];
+            }
+            for (int d = 0; d < D; ++d) lx[s][d * np + p] = lx1[d];
+            for (int i = 0; i < 3; ++i) lu[s][i * np + p] = lu0[i];
+        }
+    }
+    /* push_half_b1: B^n = B^{n-1/2} - h curl+ E -> lB unchanged, lE += -h curl- lB */
+    orc_advance_e(D, n, -h, lB, lE);
+    free(B1);
+    free(lJ);
+    return 0;
+}
