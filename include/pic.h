@@ -71,6 +71,8 @@ typedef int32_t pic_status;
 #define PIC_E_CFL (1 << 9)          /* |dx| >= 1 cell in one step          */
 #define PIC_E_NONFINITE (1 << 10)   /* NaN/Inf momentum or position        */
 #define PIC_E_OUT_OF_TILE (1 << 11) /* stored position outside its tile    */
+#define PIC_E_ADJ_MAP (1 << 12)     /* adjoint origin id beyond the target
+                                       buffer (wrong before_stride)       */
 
 #define PIC_FP32 0
 #define PIC_FP64 1
@@ -127,6 +129,14 @@ typedef struct {
  * instead of one work-group per tile; for uneven tile loads and batches of
  * boxes of different sizes. */
 #define PIC_OPT_PERSISTENT 2u
+/* pic_config.options: origin tracking for the reverse-mode adjoint.  Every
+ * fused step (and pic_init_tiles) records, per stored particle, where it
+ * came from: the slot it held before the step, or its index in the
+ * concatenated input of pic_init_tiles (boxes, then species, then input
+ * order).  Adds the ids region and the adjoint scratch to the workspace.
+ * With it, pic_push_interp requires PIC_FUSED and PIC_SORT_CELLS is
+ * rejected (neither path records origins). */
+#define PIC_OPT_TRACK 4u
 
 /* Byte offsets of the regions inside the caller's workspace.  Fields:
  * [3][cells_total] each, boxes concatenated (box b starts at cell offset
@@ -144,6 +154,8 @@ typedef struct {
     uint64_t off_seg_count;                 /* int32 [tiles][species]          */
     uint64_t off_error;                     /* int32 latched device error bits */
     uint64_t off_flags;                     /* int64 near-face counter          */
+    uint64_t off_ids;                       /* int32 [capacity_total] origin of
+                                               each particle (PIC_OPT_TRACK)   */
     int64_t cells_total;
     int64_t tiles_total;
     int64_t capacity_total;
@@ -244,6 +256,41 @@ pic_status pic_error(pic_ctx *ctx);
 /* FP64 diagnostics of the current state.  Synchronises the stream.  Its
  * return value includes the latched device error bits (then cleared). */
 pic_status pic_diagnostics(pic_ctx *ctx, pic_diag *out);
+
+/* Reverse mode.  The adjoint of one step maps the sensitivities of a loss
+ * to the state after the step (x^{n+1}, u^{n+1/2}, E^{n+1}, B^{n+1/2}) to
+ * those of the state before it (x^n, u^{n-1/2}, E^n, B^{n-1/2}): the
+ * transposed Jacobian of every Table-1 row taken in reverse order
+ * (add_cur, push_e, push_half_b2, comp_curr of App. D, the position update
+ * of Eq. fdX, the Boris update of App. C, interp_em of Sect. 2.3.2,
+ * push_half_b1), with the transposed curls (curl+)^T = curl- on the
+ * periodic Yee lattice.  Adjoint arrays are device buffers in the working
+ * precision with the layouts of the state: particles [dim|3][capacity_total]
+ * (segment slots), fields [3][cells_total].  Both calls need PIC_OPT_TRACK
+ * and only enqueue work; device-side problems are latched as in forward
+ * steps.  Reverse a step from a saved copy of the workspace: the caller
+ * restores the state after the step and calls pic_adjoint_unpermute, then
+ * restores the state before it and calls pic_adjoint_step. */
+
+/* Move particle adjoints from the slots of the current state to where each
+ * particle came from (the ids region): lpos_after/lu_after are indexed by
+ * the current slots; lpos_before/lu_before ([dim|3][before_stride]) receive
+ * them at the origin slots.  before_stride = capacity_total after a step;
+ * after pic_init_tiles it is the total input count, and the output is in
+ * the concatenated input order.  Entries of lpos_before/lu_before that no
+ * particle maps to are left unchanged.  The buffers must not overlap. */
+pic_status pic_adjoint_unpermute(pic_ctx *ctx, const void *lpos_after, const void *lu_after, void *lpos_before,
+                                 void *lu_before, int64_t before_stride);
+
+/* Reverse the fused step (PIC_FUSED | PIC_PUSH_HALF_B, the same arithmetic
+ * as without PIC_PUSH_HALF_B) taken from the current state.  On entry
+ * lpos, lu hold the adjoints of x^{n+1}, u^{n+1/2} at the slots of the
+ * particles in the current state (after pic_adjoint_unpermute), lE, lB
+ * those of E^{n+1}, B^{n+1/2}; on return, in place, the adjoints of the
+ * current state.  The state itself is not modified.  Particles stopped by a
+ * latched device error (non-finite, CFL, outside the tile) keep their
+ * adjoint unchanged. */
+pic_status pic_adjoint_step(pic_ctx *ctx, void *lpos, void *lu, void *lE, void *lB);
 
 /* Release the host context (the workspace stays the caller's). */
 pic_status pic_destroy(pic_ctx *ctx);

@@ -15,6 +15,7 @@ PIC_E_CAPACITY = 1 << 8
 PIC_E_CFL = 1 << 9
 PIC_E_NONFINITE = 1 << 10
 PIC_E_OUT_OF_TILE = 1 << 11
+PIC_E_ADJ_MAP = 1 << 12
 PIC_FP32 = 0
 PIC_FP64 = 1
 PIC_MAX_SPECIES = 4
@@ -28,10 +29,11 @@ PIC_SORT_CELLS = 2
 PIC_PUSH_HALF_B = 4
 PIC_OPT_ACC_WORKING = 1
 PIC_OPT_PERSISTENT = 2
+PIC_OPT_TRACK = 4
 
 EXPORTS = ["pic_query", "pic_init_tiles", "pic_fdtd_step", "pic_push_interp", "pic_deposit_current",
            "pic_sort_migrate", "pic_step", "pic_graph_capture", "pic_graph_launch", "pic_error",
-           "pic_diagnostics", "pic_destroy", "pic_last_error"]
+           "pic_diagnostics", "pic_adjoint_unpermute", "pic_adjoint_step", "pic_destroy", "pic_last_error"]
 
 P = ctypes.c_void_p
 I32 = ctypes.c_int32
@@ -54,7 +56,7 @@ class PicLayout(ctypes.Structure):
     _fields_ = [
         ("total_bytes", U64), ("off_E", U64), ("off_B", U64), ("off_J", U64), ("off_pos", U64),
         ("off_u", U64), ("off_xold", U64), ("off_seg_offset", U64), ("off_seg_capacity", U64),
-        ("off_seg_count", U64), ("off_error", U64), ("off_flags", U64),
+        ("off_seg_count", U64), ("off_error", U64), ("off_flags", U64), ("off_ids", U64),
         ("cells_total", I64), ("tiles_total", I64), ("capacity_total", I64), ("outbox_capacity", I64),
         ("elem_bytes", I32), ("reserved", I32),
     ]
@@ -99,6 +101,8 @@ def lib():
             "pic_graph_launch": [P],
             "pic_error": [P],
             "pic_diagnostics": [P, P],
+            "pic_adjoint_unpermute": [P, P, P, P, P, I64],
+            "pic_adjoint_step": [P, P, P, P, P],
             "pic_destroy": [P],
             "pic_last_error": [],
         }

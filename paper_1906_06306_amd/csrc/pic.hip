@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/pic.h"
+#include "pic_adjoint.hpp"
 #include "pic_aux_kernels.hpp"
 
 using pic::Params;
@@ -54,6 +55,8 @@ struct Layout {
     uint64_t off_tmp, off_jblk, off_rblk, off_part, off_ob_pos, off_ob_u, off_ob_dir, off_ob_cnt;
     uint64_t off_tiles, off_charge, off_qm, off_mass, off_order, off_queue;
     uint64_t off_key, off_xl, off_hist;
+    uint64_t off_ob_ids, off_adj_lj, off_adj_eblk, off_adj_bblk;
+    int64_t fblk_cells, n_input;
     int64_t jblk_cells, rblk_cells, max_count, max_ntb, nchunks_max, ob_dir_stride;
     std::vector<TileDesc> tiles;
     std::vector<int64_t> seg_off;
@@ -177,6 +180,14 @@ pic_status make_layout(const pic_config *c, const int64_t *counts, Layout &L)
     L.jblk_cells = cb;
     L.rblk_cells = rb;
     L.nchunks_max = std::min<int64_t>(2048, std::max<int64_t>(1, (L.max_count + 4095) / 4096));
+    int64_t fbk = 1;
+    for (int d = 0; d < D; ++d) fbk *= T[d] + 2;
+    L.fblk_cells = fbk;
+    L.n_input = 0;
+    for (int i = 0; i < nb * ns; ++i) L.n_input += counts[i];
+    const bool track = (c->options & PIC_OPT_TRACK) != 0;
+    if (track && (cap_total > INT32_MAX || L.n_input > INT32_MAX))
+        return fail(PIC_E_ARG, "origin tracking stores int32 ids: at most 2^31-1 slots and input particles");
 
     uint64_t off = 0;
     auto take = [&](uint64_t bytes) {
@@ -197,6 +208,7 @@ pic_status make_layout(const pic_config *c, const int64_t *counts, Layout &L)
     P.off_seg_count = take(tiles * ns * 4);
     P.off_error = take(4);
     P.off_flags = take(8);
+    P.off_ids = take(track ? cap_total * 4 : 0);
     L.off_tmp = take((D + 3) * cap_total * w);
     L.off_jblk = take(tiles * 3 * cb * w);
     L.off_rblk = take(tiles * rb * 8);
@@ -215,6 +227,10 @@ pic_status make_layout(const pic_config *c, const int64_t *counts, Layout &L)
     L.off_key = take(L.max_count * 4);
     L.off_xl = take(D * L.max_count * w);
     L.off_hist = take(L.nchunks_max * L.max_ntb * 4);
+    L.off_ob_ids = take(track ? tiles * ns * obcap * 4 : 0);
+    L.off_adj_lj = take(track ? 3 * cells * w : 0);
+    L.off_adj_eblk = take(track ? tiles * 3 * cb * w : 0);
+    L.off_adj_bblk = take(track ? tiles * 3 * fbk * w : 0);
     P.total_bytes = off;
     P.cells_total = cells;
     P.tiles_total = tiles;
@@ -230,6 +246,7 @@ struct pic_ctx {
     int D, prec, ns, nb, block;
     bool acc_working;   // LDS current block in the working precision
     bool persistent;    // push as a persistent tile walker
+    bool track;         // origin tracking and adjoint scratch present
     int n_cu;           // compute units of the device
     hipGraphExec_t graph;   // captured steps, or null
     int graph_steps;
@@ -281,6 +298,10 @@ Params<R> params(pic_ctx *x)
     p.nearface = reinterpret_cast<unsigned long long *>(ws + L.pub.off_flags);
     p.queue = reinterpret_cast<int32_t *>(ws + L.off_queue);
     p.order = reinterpret_cast<const int32_t *>(ws + L.off_order);
+    if (x->track) {
+        p.ids = reinterpret_cast<int32_t *>(ws + L.pub.off_ids);
+        p.ob_ids = reinterpret_cast<int32_t *>(ws + L.off_ob_ids);
+    }
     return p;
 }
 
@@ -431,6 +452,7 @@ struct Impl {
         if (!st) st = fill<R>(x, p.B, 3 * L.pub.cells_total, R(0));
         if (!st) st = fill<R>(x, p.jblk, L.pub.tiles_total * 3 * L.jblk_cells, R(0));
         if (st) return st;
+        int64_t id_base = 0;
         for (int b = 0; b < x->nb; ++b) {
             const TileDesc &t0 = L.tiles[L.box_tile0[b]];
             const int64_t cells = (int64_t)t0.n[0] * t0.n[1] * t0.n[2];
@@ -444,6 +466,7 @@ struct Impl {
             HIP_OK(hipGetLastError());
             for (int s = 0; s < x->ns; ++s) {
                 const int64_t count = counts[b * x->ns + s];
+                id_base += count;
                 if (count == 0) continue;
                 if (!in->pos || !in->u || !in->pos[b * x->ns + s] || !in->u[b * x->ns + s])
                     return fail(PIC_E_ARG, "missing particle data for box %d species %d", b, s);
@@ -457,6 +480,7 @@ struct Impl {
                 g.count = count;
                 g.nchunks = (int32_t)std::min<int64_t>(L.nchunks_max, std::max<int64_t>(1, (count + 4095) / 4096));
                 g.chunk = (int32_t)((count + g.nchunks - 1) / g.nchunks);
+                g.id_base = id_base - count;
                 int kgrid = (int)std::min<int64_t>((count + 255) / 256, 16384);
                 hipLaunchKernelGGL((pic::k_bin_keys<R, D>), dim3(kgrid), dim3(256), 0, x->stream, g, in->pos[b * x->ns + s],
                                    key, xl, p.err, p.nearface);
@@ -473,6 +497,57 @@ struct Impl {
                 HIP_OK(hipGetLastError());
             }
         }
+        return PIC_OK;
+    }
+
+    // Reverse of one fused step from the current state (Table 1 rows in
+    // reverse order; the field rows reuse the forward stencils on the
+    // adjoint fields, since (curl+)^T = curl- on the periodic lattice).
+    static pic_status adjoint(pic_ctx *x, void *lpos, void *lu, void *lE, void *lB)
+    {
+        Params<R> p = params<R>(x);
+        const Layout &L = x->L;
+        pic::AdjParams<R> a{};
+        a.lpos = reinterpret_cast<R *>(lpos);
+        a.lu = reinterpret_cast<R *>(lu);
+        a.lE = reinterpret_cast<R *>(lE);
+        a.lB = reinterpret_cast<R *>(lB);
+        a.lJ = reinterpret_cast<R *>(x->ws + L.off_adj_lj);
+        a.eblk = reinterpret_cast<R *>(x->ws + L.off_adj_eblk);
+        a.bblk = reinterpret_cast<R *>(x->ws + L.off_adj_bblk);
+        const R c = (R)x->c;
+        const int64_t n3 = 3 * L.pub.cells_total;
+        dim3 g((unsigned)L.pub.tiles_total), b(256);
+        // add_cur: E^{n+1} = ... - J  ->  lambda_J = -lambda_E
+        hipLaunchKernelGGL((pic::k_adj_neg<R>), dim3((unsigned)std::min<int64_t>((n3 + 255) / 256, 8192)), b, 0,
+                           x->stream, a.lJ, a.lE, n3);
+        // push_e: E^{n+1} = E^n + c curl- B^{n+1/2}  ->  lambda_B += c curl+ lambda_E
+        Params<R> q = p;
+        q.E = a.lE;
+        q.B = a.lB;
+        hipLaunchKernelGGL((pic::k_field<R, D, 0>), g, b, 0, x->stream, q, -c);
+        // push_half_b2: B^{n+1/2} = B^n - (c/2) curl+ E^n  ->  lambda_E -= (c/2) curl- lambda_B
+        hipLaunchKernelGGL((pic::k_field<R, D, 1>), g, b, 0, x->stream, q, R(-0.5) * c);
+        // comp_curr, position update, Boris, interp_em per particle
+        const size_t lds = 3 * (L.jblk_cells + L.fblk_cells) * sizeof(double) +
+                           (6 * L.jblk_cells + 3 * L.fblk_cells) * sizeof(R);
+        pic_status st = set_lds(pic::k_adj_push<R, D>, lds);
+        if (st) return st;
+        hipLaunchKernelGGL((pic::k_adj_push<R, D>), g, b, lds, x->stream, p, a);
+        hipLaunchKernelGGL((pic::k_adj_fold<R, D>), g, b, 0, x->stream, p, a);
+        // push_half_b1: B^n = B^{n-1/2} - (c/2) curl+ E^n  ->  lambda_E -= (c/2) curl- lambda_B^n
+        hipLaunchKernelGGL((pic::k_field<R, D, 1>), g, b, 0, x->stream, q, R(-0.5) * c);
+        HIP_OK(hipGetLastError());
+        return PIC_OK;
+    }
+
+    static pic_status unpermute(pic_ctx *x, const void *la, const void *ua, void *lb, void *ub, int64_t stride)
+    {
+        Params<R> p = params<R>(x);
+        hipLaunchKernelGGL((pic::k_adj_unpermute<R, D>), dim3((unsigned)x->L.pub.tiles_total), dim3(256), 0,
+                           x->stream, p, reinterpret_cast<const R *>(la), reinterpret_cast<const R *>(ua),
+                           reinterpret_cast<R *>(lb), reinterpret_cast<R *>(ub), stride);
+        HIP_OK(hipGetLastError());
         return PIC_OK;
     }
 
@@ -533,6 +608,11 @@ pic_status do_push(pic_ctx *x, bool fused, bool halfb) { PIC_DISPATCH(x, push(x,
 pic_status do_deposit(pic_ctx *x, bool unfused) { PIC_DISPATCH(x, deposit(x, unfused)); }
 pic_status do_migrate(pic_ctx *x, bool out, bool in, bool sort) { PIC_DISPATCH(x, migrate(x, out, in, sort)); }
 pic_status do_diag(pic_ctx *x, pic_diag *o) { PIC_DISPATCH(x, diag(x, o)); }
+pic_status do_adjoint(pic_ctx *x, void *a, void *b, void *c, void *d) { PIC_DISPATCH(x, adjoint(x, a, b, c, d)); }
+pic_status do_unpermute(pic_ctx *x, const void *a, const void *b, void *c, void *d, int64_t s)
+{
+    PIC_DISPATCH(x, unpermute(x, a, b, c, d, s));
+}
 
 template <typename R>
 pic_status upload_tables(pic_ctx *x, const pic_config *cfg)
@@ -571,6 +651,7 @@ pic_status error_status(int32_t bits)
     if (bits & pic::ERR_CFL) st |= PIC_E_CFL;
     if (bits & pic::ERR_NONFINITE) st |= PIC_E_NONFINITE;
     if (bits & pic::ERR_OUT_OF_TILE) st |= PIC_E_OUT_OF_TILE;
+    if (bits & pic::ERR_ADJ_MAP) st |= PIC_E_ADJ_MAP;
     if (st) fail(st, "device error bits 0x%x", bits);
     return st;
 }
@@ -612,6 +693,7 @@ pic_status pic_init_tiles(const pic_config *cfg, const int64_t *counts, void *wo
     x->block = cfg->block ? cfg->block : 256;
     x->acc_working = (cfg->options & PIC_OPT_ACC_WORKING) != 0;
     x->persistent = (cfg->options & PIC_OPT_PERSISTENT) != 0;
+    x->track = (cfg->options & PIC_OPT_TRACK) != 0;
     x->graph = nullptr;
     x->graph_steps = 0;
     {
@@ -669,6 +751,7 @@ pic_status pic_push_interp(pic_ctx *x, uint32_t flags)
     if (!x) return fail(PIC_E_ARG, "null context");
     if (x->state != 0) return fail(PIC_E_STATE, "push called before the previous push was deposited and migrated");
     const bool fused = flags & PIC_FUSED;
+    if (x->track && !fused) return fail(PIC_E_ARG, "origin tracking records origins in the fused push only");
     pic_status st = do_push(x, fused, (flags & PIC_PUSH_HALF_B) != 0);
     if (st) return st;
     x->state = fused ? 2 : 1;
@@ -694,6 +777,7 @@ pic_status pic_sort_migrate(pic_ctx *x, uint32_t flags)
     if (!x) return fail(PIC_E_ARG, "null context");
     if (x->state == 1) return fail(PIC_E_STATE, "deposit the current of an unfused push before migrating");
     const bool sort = flags & PIC_SORT_CELLS;
+    if (x->track && sort) return fail(PIC_E_ARG, "the cell sort does not record origins (PIC_OPT_TRACK)");
     pic_status st;
     if (x->state == 3) st = do_migrate(x, true, true, sort);        // unfused push: out + in
     else if (x->state == 2) st = do_migrate(x, false, true, sort);  // fused push packed already
@@ -779,6 +863,26 @@ pic_status pic_diagnostics(pic_ctx *x, pic_diag *out)
     if ((st = read_error(x, &bits))) return st;
     out->error_bits = bits;
     return error_status(bits);
+}
+
+pic_status pic_adjoint_unpermute(pic_ctx *x, const void *lpos_after, const void *lu_after, void *lpos_before,
+                                 void *lu_before, int64_t before_stride)
+{
+    if (!x) return fail(PIC_E_ARG, "null context");
+    if (!x->track) return fail(PIC_E_STATE, "the context was created without PIC_OPT_TRACK");
+    if (!lpos_after || !lu_after || !lpos_before || !lu_before || before_stride < 1)
+        return fail(PIC_E_ARG, "adjoint buffers and a positive before_stride are required");
+    if (x->state != 0) return fail(PIC_E_STATE, "unpermute must run between steps");
+    return do_unpermute(x, lpos_after, lu_after, lpos_before, lu_before, before_stride);
+}
+
+pic_status pic_adjoint_step(pic_ctx *x, void *lpos, void *lu, void *lE, void *lB)
+{
+    if (!x) return fail(PIC_E_ARG, "null context");
+    if (!x->track) return fail(PIC_E_STATE, "the context was created without PIC_OPT_TRACK");
+    if (!lpos || !lu || !lE || !lB) return fail(PIC_E_ARG, "adjoint buffers are required");
+    if (x->state != 0) return fail(PIC_E_STATE, "the adjoint step must start between steps");
+    return do_adjoint(x, lpos, lu, lE, lB);
 }
 
 pic_status pic_destroy(pic_ctx *x)

@@ -33,6 +33,7 @@ struct BinGeom {
     int64_t count;        // particles of this (box, species)
     int32_t nchunks;
     int32_t chunk;        // particles per chunk
+    int64_t id_base;      // origin id of input particle 0 of this (box, species)
 };
 
 template <typename R>
@@ -153,6 +154,7 @@ __global__ void __launch_bounds__(64) k_bin_scatter(BinGeom g, const int32_t *ke
                 for (int d = 0; d < D; ++d) p.pos[d * cap + dst] = xl[d * g.count + i];
 #pragma unroll
                 for (int mm = 0; mm < 3; ++mm) p.u[mm * cap + dst] = (R)u64[mm * g.count + i];
+                if (p.ids) p.ids[dst] = (int32_t)(g.id_base + i);   // index in the concatenated input
             }
         }
     }

@@ -55,9 +55,11 @@ struct Params {
     unsigned long long *nearface;
     int32_t *queue;           // work counter of the persistent walker
     const int32_t *order;     // tile visiting order of the persistent walker
+    int32_t *ids;             // [cap_total] origin of each particle, or null
+    int32_t *ob_ids;          // [tile*species][ob_cap] origin of each leaver
 };
 
-enum : int32_t { ERR_CAPACITY = 1, ERR_CFL = 2, ERR_NONFINITE = 4, ERR_OUT_OF_TILE = 8 };
+enum : int32_t { ERR_CAPACITY = 1, ERR_CFL = 2, ERR_NONFINITE = 4, ERR_OUT_OF_TILE = 8, ERR_ADJ_MAP = 16 };
 
 // ---------------------------------------------------------------- helpers
 

@@ -299,6 +299,12 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int t, unsig
 #pragma unroll
                     for (int m = 0; m < 3; ++m) du[m][k] = u[j][m];
                     p.ob_dir[(int64_t)ts * p.ob_dir_stride + (leave ? slot : p.ob_cap + lane_idx)] = code[j];
+                    if (p.ids) {
+                        // origin tracking: global slot this particle was read from
+                        const int32_t origin = (int32_t)(so + c0 + lane_idx);
+                        if (leave) p.ob_ids[ob + slot] = origin;
+                        else p.ids[so + k] = origin;
+                    }
                 }
                 const int nvalid = min(G, cnt - c0);
                 keep += tot;
@@ -606,6 +612,7 @@ __global__ void __launch_bounds__(1024) k_migrate_in(Params<R> p)
                 const int dst = cnt + pre;
                 if (dst < scap) {
                     const int64_t sts = src / p.ob_cap, k = src - sts * p.ob_cap;
+                    if (p.ids) p.ids[so + dst] = p.ob_ids[sts * p.ob_cap + k];
 #pragma unroll
                     for (int d = 0; d < D; ++d) p.pos[d * cap + so + dst] = p.ob_pos[sts * p.ob_cap * D + d * p.ob_cap + k];
 #pragma unroll

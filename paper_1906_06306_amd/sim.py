@@ -11,6 +11,13 @@ import torch
 from . import _lib as L
 
 
+def _dev64(a, device) -> torch.Tensor:
+    """Contiguous FP64 copy of a numpy array or tensor on the device."""
+    if isinstance(a, torch.Tensor):
+        return a.detach().to(device=device, dtype=torch.float64).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(device)
+
+
 @dataclass
 class Box:
     """One periodic box: FP64 global state in code units (App. A)."""
@@ -61,7 +68,7 @@ class PicSim:
         self._charge = np.array([b.charge for b in boxes], dtype=np.float64)
         self._qm = np.array([b.qm for b in boxes], dtype=np.float64)
         self._mass = np.array([b.mass for b in boxes], dtype=np.float64)
-        self._counts = np.array([[p.shape[1] for p in b.pos] for b in boxes], dtype=np.int64)
+        self._counts = np.array([[int(p.shape[1]) for p in b.pos] for b in boxes], dtype=np.int64)
         self._tcap = None if tile_capacity is None else np.ascontiguousarray(tile_capacity, dtype=np.int64)
         cfg = L.PicConfig()
         cfg.dim = self.D
@@ -93,13 +100,13 @@ class PicSim:
         pos_ptrs, u_ptrs, e_ptrs, b_ptrs = [], [], [], []
         for b in boxes:
             for s in range(self.ns):
-                pt = torch.as_tensor(np.ascontiguousarray(b.pos[s], dtype=np.float64)).to(self.device)
-                ut = torch.as_tensor(np.ascontiguousarray(b.u[s], dtype=np.float64)).to(self.device)
+                pt = _dev64(b.pos[s], self.device)
+                ut = _dev64(b.u[s], self.device)
                 keep += [pt, ut]
                 pos_ptrs.append(pt.data_ptr())
                 u_ptrs.append(ut.data_ptr())
-            et = torch.as_tensor(np.ascontiguousarray(b.E, dtype=np.float64)).to(self.device)
-            bt = torch.as_tensor(np.ascontiguousarray(b.B, dtype=np.float64)).to(self.device)
+            et = _dev64(b.E, self.device)
+            bt = _dev64(b.B, self.device)
             keep += [et, bt]
             e_ptrs.append(et.data_ptr())
             b_ptrs.append(bt.data_ptr())
@@ -155,6 +162,52 @@ class PicSim:
         fn = L.lib().pic_graph_launch
         for _ in range(n):
             L.check(fn(self.ctx))
+
+    # ------------------------------------------------------ reverse mode
+    def snapshot(self) -> torch.Tensor:
+        """Copy of the whole workspace (state, tables and origin ids)."""
+        return self.ws.clone()
+
+    def restore(self, snap: torch.Tensor):
+        self.ws.copy_(snap)
+
+    def adjoint_buffers(self):
+        """Zeroed particle and field adjoint arrays in the state layout."""
+        cap = int(self.layout.capacity_total)
+        N = int(self.layout.cells_total)
+        z = lambda *shape: torch.zeros(shape, dtype=self.dtype, device=self.device)
+        return z(self.D, cap), z(3, cap), z(3, N), z(3, N)
+
+    @property
+    def n_input(self) -> int:
+        return int(self._counts.sum())
+
+    def unpermute(self, lpos_a, lu_a, lpos_b, lu_b, stride: int):
+        for t in (lpos_a, lu_a, lpos_b, lu_b):
+            assert t.dtype == self.dtype and t.is_contiguous() and t.device == self.device
+        assert lpos_b.shape[-1] == stride and lu_b.shape[-1] == stride
+        L.check(L.lib().pic_adjoint_unpermute(self.ctx, lpos_a.data_ptr(), lu_a.data_ptr(), lpos_b.data_ptr(),
+                                              lu_b.data_ptr(), int(stride)))
+
+    def adjoint_step(self, lpos, lu, lE, lB):
+        for t in (lpos, lu, lE, lB):
+            assert t.dtype == self.dtype and t.is_contiguous() and t.device == self.device
+        L.check(L.lib().pic_adjoint_step(self.ctx, lpos.data_ptr(), lu.data_ptr(), lE.data_ptr(), lB.data_ptr()))
+
+    def input_slices(self):
+        """(box, species) -> slice of the concatenated input order."""
+        out, o = {}, 0
+        for b in range(self.nb):
+            for s in range(self.ns):
+                c = int(self._counts[b, s])
+                out[(b, s)] = slice(o, o + c)
+                o += c
+        return out
+
+    def ids_host(self):
+        torch.cuda.synchronize(self.device)
+        cap = int(self.layout.capacity_total)
+        return self._view(self.layout.off_ids, cap, torch.int32).cpu().numpy()
 
     def error(self) -> int:
         code = L.lib().pic_error(self.ctx)
