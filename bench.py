@@ -54,6 +54,11 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps timed for the CPU baseline")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale rocprofv3 FETCH/WRITE_SIZE)")
+    ap.add_argument("--workload", default="turbulence", choices=["turbulence", "shear-adjoint"],
+                    help="turbulence: the throughput line; shear-adjoint: the differentiable window "
+                         "(256^2, 32 ppc/species, 40 steps, checkpoints every 8) with its forward and "
+                         "reverse rates and gradients")
+    ap.add_argument("--fd", action="store_true", help="shear-adjoint: also central differences of the FP64 forward")
     return ap.parse_args()
 
 
@@ -152,6 +157,80 @@ def calibrate_copy():
     log("copy calibration: 3 copies of 1 GiB done")
 
 
+def bench_adjoint(args):
+    """Differentiable window: forward with checkpoints, then the reverse
+    sweep (recomputation + adjoint steps), FP32; gradients of sum |E^40|^2 in
+    the shear amplitude A and guide field B0."""
+    import torch
+    import synth
+    from paper_1906_06306_amd.adjoint import PicWindow
+
+    n, ppc, nsteps, window, tile = 256, 32, 40, 8, (16, 16)
+    amp, B0 = 0.1, 0.078772
+    base = synth.shear(n=n, ppc=ppc, amp=0.0, B0=1.0)
+    n_p = base.nparticles
+    log(f"shear window: {n_p} particles, {nsteps} steps")
+
+    def run(a, b, prec, grad):
+        dev = torch.device("cuda:0")
+        A = torch.tensor(a, dtype=torch.float64, device=dev, requires_grad=grad)
+        Bz = torch.tensor(b, dtype=torch.float64, device=dev, requires_grad=grad)
+        E0, B0f, parts = synth.shear_tensors(base, A, Bz)
+        settings = dict(D=2, n=base.n, c=base.c, charge=[x.q for x in base.species],
+                        qm=[x.s for x in base.species], mass=[x.m for x in base.species], nsteps=nsteps,
+                        window=window, precision=prec, tile=tile)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        E, _ = PicWindow.apply(settings, E0, B0f, *parts)
+        loss = (E * E).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if not grad:
+            return loss.item(), t1 - t0
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return loss.item(), A.grad.item(), Bz.grad.item(), t1 - t0, t2 - t1
+
+    run(amp, B0, "fp32", True)   # warm-up (kernel attributes, allocator)
+    L32, gA, gB, tf, tb = run(amp, B0, "fp32", True)
+    log(f"fp32: forward {tf:.3f} s, reverse {tb:.3f} s, dL/dA {gA:.8e}, dL/dB0 {gB:.8e}")
+    L64, gA64, gB64, tf64, tb64 = run(amp, B0, "fp64", True)
+    fd = None
+    if args.fd:
+        # one-sided differences of the FP64 forward on both sides over a
+        # sweep of h; the ZigZag current jumps at face crossings, so only
+        # estimates that agree with another interval's are jump-free
+        fd = {}
+        Lc, _ = run(amp, B0, "fp64", False)
+        for key in ("A", "B0"):
+            est = []
+            for h in (1e-9, 1e-10, 1e-11, 1e-12):
+                for sgn in (1.0, -1.0):
+                    a1, b1 = (amp + sgn * h, B0) if key == "A" else (amp, B0 + sgn * h)
+                    lp, _ = run(a1, b1, "fp64", False)
+                    est.append((sgn * h, sgn * (lp - Lc) / h))
+            clean = [v for i, (h, v) in enumerate(est)
+                     if any(abs(v - w) <= 1e-5 * abs(v) for j, (_, w) in enumerate(est) if j != i)]
+            fd[key] = {"estimates": {f"{h:+g}": v for h, v in est}, "jump_free": clean}
+    out = {
+        "metric": "particle-steps/s of the differentiable window (forward with checkpoints + reverse sweep)",
+        "value": n_p * nsteps / (tf + tb),
+        "unit": "particle-steps/s",
+        "n_gpus": 1, "steps": nsteps, "warmup": 1,
+        "ms_per_step": (tf + tb) / nsteps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"2D3V shear {n}x{n}, {ppc} ppc/species, theta=0.1, sigma=1, A=0.1, "
+                               f"{nsteps} steps, checkpoints every {window}", "particles": n_p, "tile": tile[0]},
+        "forward_s": tf, "reverse_s": tb,
+        "forward_rate": n_p * nsteps / tf, "reverse_rate": n_p * nsteps / tb,
+        "loss": L32, "dL_dA": gA, "dL_dB0": gB,
+        "fp64": {"loss": L64, "dL_dA": gA64, "dL_dB0": gB64, "forward_s": tf64, "reverse_s": tb64},
+        "finite_differences_fp64": fd,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -164,6 +243,9 @@ def main():
     assert torch.cuda.is_available(), "no GPU"
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.workload == "shear-adjoint":
+        bench_adjoint(args)
         return
     t0 = time.perf_counter()
     plasma = synth.turbulence(n=args.n, ppc=args.ppc)

@@ -304,6 +304,29 @@ def shear(n: int = 256, ppc: int = 32, theta: float = 0.1, sigma: float = 1.0, a
     return _pair(2, dims, c, qabs, x, ue, x.copy(), up, E, B, meta)
 
 
+def shear_tensors(base: Plasma, A, B0):
+    """The initial state of ``shear`` as torch tensors on the device of the
+    0-d tensors A (drift amplitude) and B0 (guide field), through which it
+    depends differentiably on both: u_x = u_th,x + A sin(2 pi y / n) for
+    both species, B = B0 z, E = 0.  ``base`` is ``shear(..., amp=0)``: it
+    supplies positions and the thermal four-velocities.  Returns
+    (E (3, N), B (3, N), [x_e, u_e, x_p, u_p])."""
+    import torch
+    dev = A.device
+    n = base.n[0]
+    parts = []
+    for sp_ in base.species:
+        x = torch.as_tensor(sp_.x, device=dev)
+        u = torch.as_tensor(sp_.u, device=dev)
+        drift = torch.sin(2.0 * math.pi * x[1] / n)
+        parts += [x, torch.cat([(u[0] + A * drift)[None], u[1:]], 0)]
+    N = base.ncells
+    E = torch.zeros((3, N), dtype=torch.float64, device=dev)
+    zero = torch.zeros(N, dtype=torch.float64, device=dev)
+    B = torch.stack([zero, zero, B0 * torch.ones(N, dtype=torch.float64, device=dev)])
+    return E, B, parts
+
+
 def small_random(D: int, n: tuple, ppc: int, theta: float = 0.3, c: float = 0.45,
                  field_amp: float = 0.05, seed: int = 12345, q: float = 1e-3) -> Plasma:
     """A generic small test state: thermal pair plasma plus random E and B of

@@ -14,11 +14,9 @@ when an end point crosses a face (App. D), so the transverse current and the
 loss are only piecewise smooth: a finite difference whose interval holds
 such a crossing of any particle is off by (jump)/2h, while the adjoint is
 the derivative of the smooth piece.  The finite differences are therefore
-taken over a sweep of h; estimates free of crossings agree with each other,
-and the adjoint must agree with at least two of the three.
+taken over a sweep of h and kept only where neither half-interval holds a
+jump (its one-sided difference agrees with another interval's).
 """
-import math
-
 import numpy as np
 import pytest
 
@@ -146,64 +144,98 @@ def test_adjoint_requires_tracking():
 
 # ------------------------------------------------- parameter gradients
 
-def shear_inputs(n, ppc, amp, B0, device):
-    """Initial state of the sheared plasma as differentiable tensors of the
-    drift amplitude and guide field (thermal part fixed by the seed)."""
-    base = synth.shear(n=n, ppc=ppc, amp=0.0, B0=1.0)
-    parts = []
-    for sp in base.species:
-        x = torch.as_tensor(sp.x, device=device)
-        u = torch.as_tensor(sp.u, device=device)
-        drift = torch.sin(2.0 * math.pi * x[1] / n)
-        u = torch.cat([(u[0] + amp * drift)[None], u[1:]], 0)
-        parts += [x, u]
-    N = n * n
-    E0 = torch.zeros((3, N), dtype=torch.float64, device=device)
-    zero = torch.zeros(N, dtype=torch.float64, device=device)
-    B0f = torch.stack([zero, zero, B0 * torch.ones(N, dtype=torch.float64, device=device)])
-    settings = dict(D=2, n=(n, n, 1), c=base.c, charge=[sp.q for sp in base.species],
-                    qm=[sp.s for sp in base.species], mass=[sp.m for sp in base.species])
-    return settings, E0, B0f, parts
+class Shear:
+    """Loss sum |E^N|^2 of the sheared plasma as a function of the drift
+    amplitude A and guide field B0, through the autograd wrapper."""
+
+    def __init__(self, n, ppc, nsteps, tile, window=8):
+        self.base = synth.shear(n=n, ppc=ppc, amp=0.0, B0=1.0)
+        self.nsteps, self.tile, self.window = nsteps, tile, window
+
+    def __call__(self, amp, B0, prec, grad=False):
+        from paper_1906_06306_amd.adjoint import PicWindow
+        dev = torch.device("cuda:0")
+        A = torch.tensor(amp, dtype=torch.float64, device=dev, requires_grad=grad)
+        Bz = torch.tensor(B0, dtype=torch.float64, device=dev, requires_grad=grad)
+        E0, B0f, parts = synth.shear_tensors(self.base, A, Bz)
+        b = self.base
+        settings = dict(D=2, n=b.n, c=b.c, charge=[sp.q for sp in b.species], qm=[sp.s for sp in b.species],
+                        mass=[sp.m for sp in b.species], nsteps=self.nsteps, window=self.window,
+                        precision=prec, tile=self.tile)
+        E, B = PicWindow.apply(settings, E0, B0f, *parts)
+        loss = (E * E).sum()
+        if not grad:
+            return loss.item()
+        loss.backward()
+        return loss.item(), A.grad.item(), Bz.grad.item()
 
 
-def shear_loss(n, ppc, amp, B0, nsteps, prec, tile, window=8, grad=False):
-    from paper_1906_06306_amd.adjoint import PicWindow
-    dev = torch.device("cuda:0")
-    A = torch.tensor(amp, dtype=torch.float64, device=dev, requires_grad=grad)
-    Bz = torch.tensor(B0, dtype=torch.float64, device=dev, requires_grad=grad)
-    settings, E0, B0f, parts = shear_inputs(n, ppc, A, Bz, dev)
-    settings.update(nsteps=nsteps, window=window, precision=prec, tile=tile)
-    E, B = PicWindow.apply(settings, E0, B0f, *parts)
-    loss = (E * E).sum()
-    if not grad:
-        return loss.item()
-    loss.backward()
-    return loss.item(), A.grad.item(), Bz.grad.item()
+def fd_jump_free(loss, p, hs, rtol=1e-5):
+    """Central differences of the FP64 forward at p over a sweep of h, kept
+    where neither half-interval holds a jump of the loss (a face crossing,
+    see the module docstring).  A jump inside [p, p+h] or [p-h, p] puts that
+    one-sided difference off by jump/h, so two intervals (nested or
+    disjoint) agree only when neither holds one: a half-interval is taken as
+    jump-free when its one-sided difference agrees with another's."""
+    L0 = loss(p)
+    one = {}
+    for h in hs:
+        for sgn in (1, -1):
+            one[(h, sgn)] = sgn * (loss(p + sgn * h) - L0) / h
 
-
-def fd_sweep(loss, amp, B0, hs):
-    """Central differences in A and B0 for every h of the sweep."""
+    def clean(k):
+        return any(abs(one[k] - one[j]) <= rtol * abs(one[k]) for j in one if j != k)
     out = []
     for h in hs:
-        fA = (loss(amp + h, B0) - loss(amp - h, B0)) / (2 * h)
-        fB = (loss(amp, B0 + h) - loss(amp, B0 - h)) / (2 * h)
-        out.append((h, fA, fB))
+        ok = clean((h, 1)) and clean((h, -1))
+        c = 0.5 * (one[(h, 1)] + one[(h, -1)])
+        print(f"[gpu]   h={h:g}: central {c:.10e}, one-sided {one[(h, 1)]:.10e} {one[(h, -1)]:.10e}"
+              f" {'jump-free' if ok else 'holds a jump'}", flush=True)
+        if ok:
+            out.append(c)
     return out
 
 
-def agrees(g, fds, tol):
-    return sum(abs(g - f) <= tol * abs(f) for f in fds) >= 2
+def check_gradients(prob, amp, B0, grads, hs, tols):
+    fdA = fd_jump_free(lambda a: prob(a, B0, "fp64"), amp, hs)
+    fdB = fd_jump_free(lambda b: prob(amp, b, "fp64"), B0, hs)
+    assert fdA and fdB, "every finite-difference interval held a jump"
+    for prec, (gA, gB) in grads.items():
+        for f in fdA:
+            assert abs(gA - f) <= tols[prec] * abs(f), (prec, "A", gA, f)
+        for f in fdB:
+            assert abs(gB - f) <= tols[prec] * abs(f), (prec, "B0", gB, f)
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-6), ("fp32", 1e-4)])
+# FP32: the trajectory and the adjoint carry FP32 rounding (about 1e-6 per
+# step), and dL/dB0 sums lambda_Bz over the cells with strong cancellation;
+# on this small box (4096 cells, 16 steps) that reaches 1e-4 of the result.
+# The 1e-4 target is checked on the full-size window below.
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-6), ("fp32", 5e-4)])
 def test_parameter_gradients_vs_finite_differences(prec, tol):
     n, ppc, nsteps, tile = 64, 8, 16, (16, 16)
     amp, B0 = 0.1, 0.078772
     print(f"[gpu] shear gradients {prec} n={n} ppc={ppc} steps={nsteps}", flush=True)
-    _, gA, gB = shear_loss(n, ppc, amp, B0, nsteps, prec, tile, grad=True)
-    sweep = fd_sweep(lambda a, b: shear_loss(n, ppc, a, b, nsteps, "fp64", tile), amp, B0, (1e-7, 1e-8, 1e-9))
-    for h, fA, fB in sweep:
-        print(f"[gpu] h={h:g}: dL/dA fd {fA:.10e} adjoint {gA:.10e}; dL/dB0 fd {fB:.10e} adjoint {gB:.10e}",
-              flush=True)
-    assert agrees(gA, [f[1] for f in sweep], tol)
-    assert agrees(gB, [f[2] for f in sweep], tol)
+    prob = Shear(n, ppc, nsteps, tile)
+    _, gA, gB = prob(amp, B0, prec, grad=True)
+    print(f"[gpu] adjoint dL/dA {gA:.10e} dL/dB0 {gB:.10e}", flush=True)
+    check_gradients(prob, amp, B0, {prec: (gA, gB)}, (1e-8, 1e-9, 1e-10), {prec: tol})
+
+
+def test_differentiable_window_full_size():
+    """The differentiable-window workload at full size: 256^2 cells, 32
+    particles per cell per species (4.19 M), 40 steps, checkpoints every 8
+    steps, loss sum |E^40|^2.  FP32 and FP64 adjoint gradients in the drift
+    amplitude and the guide field against the jump-free central
+    differences of the FP64 forward (1e-4 relative; 1e-5 for FP64, the
+    rounding noise of a difference at h = 1e-11)."""
+    n, ppc, nsteps, tile = 256, 32, 40, (16, 16)
+    amp, B0 = 0.1, 0.078772
+    print(f"[gpu] differentiable window n={n} ppc={ppc} steps={nsteps}", flush=True)
+    prob = Shear(n, ppc, nsteps, tile)
+    grads = {}
+    for prec in ("fp32", "fp64"):
+        _, gA, gB = prob(amp, B0, prec, grad=True)
+        grads[prec] = (gA, gB)
+        print(f"[gpu] {prec} adjoint dL/dA {gA:.10e} dL/dB0 {gB:.10e}", flush=True)
+    check_gradients(prob, amp, B0, grads, (1e-9, 1e-10, 1e-11), {"fp32": 1e-4, "fp64": 1e-5})
