@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/pic.h"
@@ -355,14 +356,14 @@ struct Impl {
         return PIC_OK;
     }
 
-    template <bool FUSED, bool HALFB, typename A>
-    static pic_status push_with(pic_ctx *x)
+    template <bool FUSED, bool HALFB, typename A, int TC>
+    static pic_status push_launch(pic_ctx *x)
     {
         Params<R> p = params<R>(x);
         size_t lds = push_lds(x, FUSED, sizeof(A));
         dim3 b(x->block);
         if (x->persistent) {
-            auto kern = pic::k_push_persistent<R, D, FUSED, HALFB, A, PUSH_UNROLL>;
+            auto kern = pic::k_push_persistent<R, D, FUSED, HALFB, A, PUSH_UNROLL, TC>;
             pic_status st = set_lds(kern, lds);
             if (st) return st;
             int per_cu = 0;
@@ -373,13 +374,30 @@ struct Impl {
             if (st) return st;
             hipLaunchKernelGGL(kern, dim3((unsigned)grid), b, lds, x->stream, p);
         } else {
-            auto kern = pic::k_push<R, D, FUSED, HALFB, A, PUSH_UNROLL>;
+            auto kern = pic::k_push<R, D, FUSED, HALFB, A, PUSH_UNROLL, TC>;
             pic_status st = set_lds(kern, lds);
             if (st) return st;
             hipLaunchKernelGGL(kern, dim3((unsigned)x->L.pub.tiles_total), b, lds, x->stream, p);
         }
         HIP_OK(hipGetLastError());
         return PIC_OK;
+    }
+
+    // The fused push with FP64 accumulation is compiled for the common cubic
+    // tile edges with the edge as a constant; other shapes use the
+    // runtime-edge kernel.
+    template <bool FUSED, bool HALFB, typename A>
+    static pic_status push_with(pic_ctx *x)
+    {
+        if constexpr (FUSED && std::is_same<A, double>::value) {
+            bool cubic = true;
+            for (int d = 1; d < D; ++d) cubic = cubic && x->T[d] == x->T[0];
+            if (cubic && x->T[0] == 8) return push_launch<FUSED, HALFB, A, 8>(x);
+            if (cubic && x->T[0] == 16) return push_launch<FUSED, HALFB, A, 16>(x);
+            if constexpr (D < 3)
+                if (cubic && x->T[0] == 32) return push_launch<FUSED, HALFB, A, 32>(x);
+        }
+        return push_launch<FUSED, HALFB, A, 0>(x);
     }
 
     static pic_status push(pic_ctx *x, bool fused, bool halfb)

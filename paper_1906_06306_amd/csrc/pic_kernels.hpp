@@ -142,18 +142,30 @@ __device__ __forceinline__ void compact_chunk(const Params<R> &p, int ts, int64_
 // c0 + j*blockDim + t), so every load and store instruction stays
 // coalesced while U loads per array are in flight; the stable compaction
 // runs once per group.
-template <typename R, int D, bool FUSED, bool HALFB, typename A, int U>
+template <typename R, int D, bool FUSED, bool HALFB, typename A, int U, int TC>
 __device__ __forceinline__ void push_tile(const Params<R> &p, const int t, unsigned char *smem)
 {
     const TileDesc td = p.tiles[t];
-    const FieldBox<D> fb(p.T);
-    const CurBox<D> cb(p.T);
+    // tile edge: a compile-time constant when TC > 0 (strides, LDS offsets
+    // and the halves T/2 then fold into the instructions), else the runtime one
+    int32_t T[3];
+    if constexpr (TC > 0) {
+        T[0] = TC;
+        T[1] = D > 1 ? TC : 1;
+        T[2] = D > 2 ? TC : 1;
+    } else {
+        T[0] = p.T[0];
+        T[1] = p.T[1];
+        T[2] = p.T[2];
+    }
+    const FieldBox<D> fb(T);
+    const CurBox<D> cb(T);
     A *sJ = reinterpret_cast<A *>(smem);
     R *sE = reinterpret_cast<R *>(sJ + (FUSED ? 3 * cb.n : 0));
     R *sB = sE + 3 * cb.n;
     int *sTot = reinterpret_cast<int *>(sB + 3 * fb.n);
-    stage_block<R, D>(p.E, p.cells_total, td, p.T, sE, cb);
-    stage_block<R, D>(p.B, p.cells_total, td, p.T, sB, fb);
+    stage_block<R, D>(p.E, p.cells_total, td, T, sE, cb);
+    stage_block<R, D>(p.B, p.cells_total, td, T, sB, fb);
     if constexpr (FUSED) {
         for (int k = threadIdx.x; k < 3 * cb.n; k += blockDim.x) sJ[k] = A(0);
     }
@@ -230,17 +242,17 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int t, unsig
                 delta[j][0] = delta[j][1] = delta[j][2] = 0;
                 code[j] = centre_code<D>();
                 if (!valid[j]) continue;
-                if (inside_tile<R, D>(x[j], p.T)) {
+                if (inside_tile<R, D>(x[j], T)) {
                     R e[3], b[3], dv[3];
-                    interp_all<R, D>(sE, cb, sB, fb, x[j], p.T, e, b);
+                    interp_all<R, D>(sE, cb, sB, fb, x[j], T, e, b);
                     boris<R>(u[j], e, b, c, inv_c, sq);
                     displacement<R>(u[j], c, dv);
 #pragma unroll
                     for (int d = 0; d < D; ++d) x2[j][d] = x[j][d] + dv[d];
-                    if (finite3<R>(u[j]) && moved_ok<R, D>(x2[j], dv, p.T)) {
+                    if (finite3<R>(u[j]) && moved_ok<R, D>(x2[j], dv, T)) {
                         if constexpr (FUSED) {
-                            zigzag<R, D, A>(sJ, cb, p.T, x[j], x2[j], dv, q);
-                            code[j] = direction_code<R, D>(x2[j], p.T, delta[j]);
+                            zigzag<R, D, A>(sJ, cb, T, x[j], x2[j], dv, q);
+                            code[j] = direction_code<R, D>(x2[j], T, delta[j]);
                         }
                     } else {
                         errs |= finite3<R>(u[j]) ? ERR_CFL : ERR_NONFINITE;
@@ -295,7 +307,7 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int t, unsig
                         }
                     }
 #pragma unroll
-                    for (int d = 0; d < D; ++d) dx[d][k] = x2[j][d] - R(delta[j][d] * p.T[d]);
+                    for (int d = 0; d < D; ++d) dx[d][k] = x2[j][d] - R(delta[j][d] * T[d]);
 #pragma unroll
                     for (int m = 0; m < 3; ++m) du[m][k] = u[j][m];
                     p.ob_dir[(int64_t)ts * p.ob_dir_stride + (leave ? slot : p.ob_cap + lane_idx)] = code[j];
@@ -339,17 +351,17 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int t, unsig
 }
 
 // One work-group per tile, tiles dispatched heaviest first.
-template <typename R, int D, bool FUSED, bool HALFB, typename A, int U>
+template <typename R, int D, bool FUSED, bool HALFB, typename A, int U, int TC>
 __global__ void __launch_bounds__(1024) k_push(Params<R> p)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    push_tile<R, D, FUSED, HALFB, A, U>(p, p.order[blockIdx.x], smem);
+    push_tile<R, D, FUSED, HALFB, A, U, TC>(p, p.order[blockIdx.x], smem);
 }
 
 // Persistent tile walker: a grid sized to the resident work-groups pulls
 // tiles (heaviest first) from an atomic counter until every tile is taken;
 // every work-group leaves the loop when the counter passes the tile count.
-template <typename R, int D, bool FUSED, bool HALFB, typename A, int U>
+template <typename R, int D, bool FUSED, bool HALFB, typename A, int U, int TC>
 __global__ void __launch_bounds__(1024) k_push_persistent(Params<R> p)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -360,7 +372,7 @@ __global__ void __launch_bounds__(1024) k_push_persistent(Params<R> p)
         const int k = next;
         __syncthreads();
         if (k >= p.ntiles) break;
-        push_tile<R, D, FUSED, HALFB, A, U>(p, p.order[k], smem);
+        push_tile<R, D, FUSED, HALFB, A, U, TC>(p, p.order[k], smem);
         __syncthreads();
     }
 }
