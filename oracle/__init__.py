@@ -49,11 +49,13 @@ def lib():
             "orc_advance_e": (None, [I, P, Dbl, P, P]),
             "orc_add_current": (None, [P, P, P]),
             "orc_interp": (None, [I, P, P, P, I64, P, P, P]),
+            "orc_interp_walls": (None, [I, P, P, P, I64, P, P, P]),
             "orc_boris": (None, [I64, Dbl, Dbl, P, P, P]),
             "orc_move": (None, [I, I64, Dbl, P, P, P]),
             "orc_zigzag": (None, [I, P, Dbl, I64, P, P, P, P]),
             "orc_wrap": (None, [I, P, I64, P]),
             "orc_step": (I, [I, P, Dbl, I, P, P, P, P, P, P, P, P]),
+            "orc_step_walls": (I, [I, P, Dbl, I, P, P, P, P, P, P, P, P]),
             "orc_rho": (None, [I, P, Dbl, I64, P, P]),
             "orc_div_edge": (None, [P, P, P]),
             "orc_div_face": (None, [P, P, P]),
@@ -104,13 +106,14 @@ def add_current(n, J, E):
 
 # --------------------------------------------------------------- particles
 
-def interp(D, n, E, B, x):
+def interp(D, n, E, B, x, walls: bool = False):
     x = _f64(x)
     np_ = x.shape[1]
     Ep = np.zeros((3, np_))
     Bp = np.zeros((3, np_))
     dims = _dims(n)
-    lib().orc_interp(D, _p(dims), _p(E), _p(B), np_, _p(x), _p(Ep), _p(Bp))
+    fn = lib().orc_interp_walls if walls else lib().orc_interp
+    fn(D, _p(dims), _p(_f64(E)), _p(_f64(B)), np_, _p(x), _p(Ep), _p(Bp))
     return Ep, Bp
 
 
@@ -187,7 +190,10 @@ class State:
         self.s = [float(s.s) for s in plasma.species]
         self.m = [float(s.m) for s in plasma.species]
 
-    def step(self, nsteps: int = 1):
+    def step(self, nsteps: int = 1, walls: bool = False):
+        """nsteps full steps; walls=True: conducting, reflecting walls at
+        x = 0 and x = n0 (y, z periodic), else periodic everywhere."""
+        fn = lib().orc_step_walls if walls else lib().orc_step
         ns = len(self.x)
         dims = _dims(self.n)
         n_per = np.array([x.shape[1] for x in self.x], dtype=np.int64)
@@ -196,7 +202,7 @@ class State:
         q = np.array(self.q, dtype=np.float64)
         s = np.array(self.s, dtype=np.float64)
         for _ in range(nsteps):
-            rc = lib().orc_step(self.D, _p(dims), self.c, ns, _p(n_per),
+            rc = fn(self.D, _p(dims), self.c, ns, _p(n_per),
                                 ctypes.cast(xp, ctypes.c_void_p), ctypes.cast(up, ctypes.c_void_p),
                                 _p(q), _p(s), _p(self.E), _p(self.B), _p(self.J))
             if rc != 0:
@@ -238,6 +244,15 @@ class State:
 
     def gauss_residual(self):
         return div_edge(self.n, self.E) - self.rho()
+
+    def hold_walls(self):
+        """Zero the wall planes (Ey, Ez, Bx at i = 0) of the fields."""
+        N = int(np.prod(_dims(self.n)))
+        n0 = self.n[0]
+        idx = np.arange(0, N, n0)
+        self.E[1, idx] = 0.0
+        self.E[2, idx] = 0.0
+        self.B[0, idx] = 0.0
 
     def div_b(self):
         return div_face(self.n, self.B)

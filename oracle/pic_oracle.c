@@ -408,6 +408,202 @@ double orc_kinetic_energy(int64_t np, double mass, double c, const double *u)
 }
 
 /* ====================================================================== */
+/* Conducting, reflecting walls in x (the shock configuration; the paper
+ * names reflecting walls for its shock runs but gives no boundary
+ * formulas, so this is the reading used throughout this implementation).
+ *
+ * The walls sit on the node planes x = 0 and x = n0; y and z stay
+ * periodic.  Tangential E (Ey, Ez) and normal B (Bx) vanish on the wall
+ * planes; storage node i = 0 holds the x = 0 plane and also stands for the
+ * x = n0 plane (which the periodic storage maps onto it), so both are held
+ * at zero.  Components staggered by 1/2 in x (Ex, By, Bz) see the wall as a
+ * mirror: their value at -1/2 equals the one at +1/2, and the one at
+ * n0 + 1/2 the one at n0 - 1/2.  A particle whose move crosses a wall is
+ * reflected (x -> -x or 2 n0 - x, u_x -> -u_x) and deposits its current
+ * along the broken path: x^n to the wall point, then the wall point to the
+ * reflected position, each piece by the ZigZag rule, which keeps the
+ * discrete continuity equation exact.                                      */
+
+static double wall_value(const int n[3], const double *F, int comp, int64_t i, int64_t j, int64_t k)
+{
+    if (stagger(comp, 0) > 0.0) {
+        /* mirror images of the half-integer sub-lattice */
+        if (i < 0) i = -1 - i;
+        if (i >= n[0]) i = 2 * (int64_t)n[0] - 1 - i;
+    } else if (i == 0 || i == n[0]) {
+        /* node-centred in x on a wall plane: Ey, Ez, Bx are zero there */
+        return 0.0;
+    }
+    return F[cell(n, i, j, k)];
+}
+
+/* interp_em with the wall images (otherwise as orc_interp) */
+void orc_interp_walls(int D, const int n[3], const double *E, const double *B, int64_t np, const double *x,
+                         double *Ep, double *Bp)
+{
+    int64_t N = ncells(n);
+    for (int64_t p = 0; p < np; ++p) {
+        for (int comp = 0; comp < 6; ++comp) {
+            const double *F = comp < 3 ? E + comp * N : B + (comp - 3) * N;
+            int64_t base[3] = {0, 0, 0};
+            double w[3] = {0.0, 0.0, 0.0};
+            for (int d = 0; d < D; ++d) {
+                double xi = x[d * np + p] - stagger(comp, d);
+                double fl = floor(xi);
+                base[d] = (int64_t)fl;
+                w[d] = xi - fl;
+            }
+            double acc = 0.0;
+            for (int cn = 0; cn < (1 << D); ++cn) {
+                int64_t idx[3] = {base[0], base[1], base[2]};
+                double wt = 1.0;
+                for (int d = 0; d < D; ++d) {
+                    int bit = (cn >> d) & 1;
+                    idx[d] += bit;
+                    wt *= bit ? w[d] : 1.0 - w[d];
+                }
+                acc += wt * wall_value(n, F, comp, idx[0], idx[1], idx[2]);
+            }
+            if (comp < 3) Ep[comp * np + p] = acc;
+            else Bp[(comp - 3) * np + p] = acc;
+        }
+    }
+}
+
+/* ZigZag deposit (App. D) of one straight move a -> b (grid dimensions)
+ * with displacement dnon along the non-grid dimensions. */
+static void zigzag_path(int D, const int n[3], double q, const double a[3], const double b[3],
+                        const double dnon[3], double *J)
+{
+    double F1[3], F2[3], W1[3] = {0, 0, 0}, W2[3] = {0, 0, 0};
+    double d1[3] = {0, 0, 0}, d2[3] = {0, 0, 0};
+    int64_t i1[3] = {0, 0, 0}, i2[3] = {0, 0, 0};
+    for (int d = 0; d < 3; ++d) {
+        if (d < D) {
+            double fa = floor(a[d]), fb = floor(b[d]);
+            double lo = fa < fb ? fa : fb, hi = fa > fb ? fa : fb;
+            double mid = 0.5 * (a[d] + b[d]);
+            double inner = hi > mid ? hi : mid;
+            double xr = (lo + 1.0) < inner ? (lo + 1.0) : inner;
+            F1[d] = q * (xr - a[d]);
+            F2[d] = q * (b[d] - xr);
+            W1[d] = 0.5 * (a[d] + xr) - fa;
+            W2[d] = 0.5 * (b[d] + xr) - fb;
+            d1[d] = xr - a[d];
+            d2[d] = b[d] - xr;
+            i1[d] = (int64_t)fa;
+            i2[d] = (int64_t)fb;
+        } else {
+            F1[d] = q * 0.5 * dnon[d];
+            F2[d] = q * 0.5 * dnon[d];
+        }
+    }
+    deposit_segment(D, n, J, F1, W1, d1, i1);
+    deposit_segment(D, n, J, F2, W2, d2, i2);
+}
+
+/* The largest double below v (v > 0). */
+static double below(double v) { return nextafter(v, 0.0); }
+
+/* One full step with walls in x, in the order of orc_step.  Positions must
+ * start inside [0, n0); E, B with the wall planes at zero (Ey, Ez, Bx at
+ * i = 0).  Returns 0, or -1 if scratch memory could not be allocated.     */
+int orc_step_walls(int D, const int n[3], double c, int nspecies, const int64_t *n_per,
+                   double **x, double **u, const double *q, const double *sgn,
+                   double *E, double *B, double *J)
+{
+    if (nspecies < 1) return -1;
+    int64_t N = ncells(n);
+    double L = (double)n[0];
+    int64_t npmax = 1;
+    for (int s = 0; s < nspecies; ++s) npmax = n_per[s] > npmax ? n_per[s] : npmax;
+    double *fp = malloc(sizeof(double) * 6 * (size_t)npmax);
+    if (!fp) return -1;
+    double **xold = calloc((size_t)nspecies, sizeof(double *));
+    double **disp = calloc((size_t)nspecies, sizeof(double *));
+    int ok = xold && disp;
+    for (int s = 0; ok && s < nspecies; ++s) {
+        xold[s] = malloc(sizeof(double) * (size_t)(D * n_per[s] + 1));
+        disp[s] = malloc(sizeof(double) * (size_t)(3 * n_per[s] + 1));
+        ok = xold[s] && disp[s];
+    }
+    if (ok) {
+        orc_advance_b(D, n, 0.5 * c, E, B);                       /* push_half_b1 */
+        for (int s = 0; s < nspecies; ++s) {                       /* interp_em, push */
+            int64_t np = n_per[s];
+            memcpy(xold[s], x[s], sizeof(double) * (size_t)(D * np));
+            orc_interp_walls(D, n, E, B, np, x[s], fp, fp + 3 * np);
+            orc_boris(np, c, sgn[s], fp, fp + 3 * np, u[s]);
+            orc_move(D, np, c, u[s], x[s], disp[s]);
+        }
+        orc_advance_b(D, n, 0.5 * c, E, B);                       /* push_half_b2 */
+        orc_advance_e(D, n, c, B, E);                             /* push_e */
+        memset(J, 0, sizeof(double) * 3 * (size_t)N);             /* comp_curr */
+        for (int s = 0; s < nspecies; ++s) {
+            int64_t np = n_per[s];
+            for (int64_t p = 0; p < np; ++p) {
+                double a[3] = {0, 0, 0}, b[3] = {0, 0, 0}, dn[3] = {0, 0, 0};
+                for (int d = 0; d < D; ++d) {
+                    a[d] = xold[s][d * np + p];
+                    b[d] = x[s][d * np + p];
+                }
+                for (int m = D; m < 3; ++m) dn[m] = disp[s][m * np + p];
+                double bx = b[0];
+                if (bx >= 0.0 && bx < L) {
+                    zigzag_path(D, n, q[s], a, b, dn, J);
+                    continue;
+                }
+                /* reflection: wall point at fraction t of the move */
+                double wx = bx < 0.0 ? 0.0 : L;
+                double t = (wx - a[0]) / (bx - a[0]);
+                double w[3] = {wx, 0, 0}, r[3] = {0, 0, 0}, dn1[3] = {0, 0, 0}, dn2[3] = {0, 0, 0};
+                for (int d = 1; d < D; ++d) w[d] = a[d] + t * (b[d] - a[d]);
+                for (int m = D; m < 3; ++m) {
+                    dn1[m] = t * dn[m];
+                    dn2[m] = dn[m] - dn1[m];
+                }
+                r[0] = bx < 0.0 ? -bx : 2.0 * L - bx;
+                if (r[0] >= L) r[0] = below(L);
+                for (int d = 1; d < D; ++d) r[d] = b[d];
+                zigzag_path(D, n, q[s], a, w, dn1, J);
+                zigzag_path(D, n, q[s], w, r, dn2, J);
+                x[s][p] = r[0];
+                u[s][p] = -u[s][p];
+            }
+        }
+        /* particle communication: periodic wrap along y and z only */
+        for (int s = 0; s < nspecies; ++s)
+            for (int d = 1; d < D; ++d) {
+                double Ld = (double)n[d];
+                for (int64_t p = 0; p < n_per[s]; ++p) {
+                    double v = x[s][d * n_per[s] + p];
+                    if (v < 0.0) v += Ld;
+                    else if (v >= Ld) v -= Ld;
+                    if (v >= Ld) v = 0.0;
+                    x[s][d * n_per[s] + p] = v;
+                }
+            }
+        orc_add_current(n, J, E);                                 /* add_cur */
+        /* the wall planes: tangential E and normal B vanish */
+        for (int k = 0; k < n[2]; ++k)
+            for (int j = 0; j < n[1]; ++j) {
+                int64_t cw = cell(n, 0, j, k);
+                E[N + cw] = 0.0;
+                E[2 * N + cw] = 0.0;
+                B[cw] = 0.0;
+            }
+    }
+    for (int s = 0; xold && disp && s < nspecies; ++s) {
+        free(xold[s]);
+        free(disp[s]);
+    }
+    free(xold);
+    free(disp);
+    free(fp);
+    return ok ? 0 : -1;
+}
+
+/* ====================================================================== */
 /* Adjoint (reverse mode) of one full step, written by hand from the
  * forward routines above.  Differentiation of the step is not in the paper;
  * these routines are the exact vector-Jacobian products of orc_step (the
