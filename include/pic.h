@@ -118,7 +118,21 @@ typedef struct {
     int32_t outbox_capacity;    /* leavers per (tile, species) per step; 0 =
                                    default (a quarter of the segment, >= 256) */
     uint32_t options;           /* PIC_OPT_* bits, 0 = defaults              */
+    const int32_t *box_walls;   /* host [n_boxes] PIC_WALL_* bits, or NULL
+                                   (every box periodic in every dimension)   */
 } pic_config;
+
+/* pic_config.box_walls: conducting, reflecting walls on the node planes
+ * x = 0 and x = n0 of the box (y, z stay periodic).  Tangential E (Ey, Ez)
+ * and normal B (Bx) are held at zero on the wall planes (pic_init_tiles
+ * zeroes them); the x-staggered components (Ex, By, Bz) see the wall as a
+ * mirror in the interpolation; a particle whose move crosses a wall is
+ * reflected (x mirrored, u_x -> -u_x) and deposits its current along the
+ * broken path to the wall point and on to the mirrored position, which
+ * keeps the continuity equation exact.  Boxes with walls need the fused
+ * push; the reverse-mode calls reject them; the Gauss diagnostic skips the
+ * wall plane (it carries the conductor's surface charge). */
+#define PIC_WALL_X 1
 
 /* pic_config.options: accumulate the tile current block in LDS in the
  * working precision instead of FP64 (the default; the block is rounded to

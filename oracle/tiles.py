@@ -11,8 +11,9 @@ permutations, migration counts) can be checked bit-exactly:
 
 * binning: tile t_d = floor(x_d / T_d); local x = fl_p(x - centre) with the
   centre t_d T_d + T_d/2 (the subtraction is exact in FP64); a value that
-  rounds to +T_d/2 belongs to the next tile at -T_d/2.  Order inside a tile
-  is the input order (stable).
+  rounds to +T_d/2 belongs to the next tile at -T_d/2 (with walls in x,
+  except across the wall at x = n0: it stays just below the face).  Order
+  inside a tile is the input order (stable).
 * migration after a push: a particle whose local coordinate left
   [-T/2, T/2) moves to the neighbour tile (offset delta in {-1,0,1}^D) with
   local x - delta T (exact).  New order inside tile r: its stayers in their
@@ -37,11 +38,14 @@ def tile_linear(tc, nt):
     return tc[0] + nt[0] * (tc[1] + nt[1] * tc[2])
 
 
-def bin_global(x, n, T, D, dtype):
+def bin_global(x, n, T, D, dtype, walls=False):
     """Bin global FP64 positions (D, np) into tiles.
 
     Returns (tile_id (np,), x_loc (D, np) in dtype, order) where ``order`` is
-    the stable permutation that groups particles by tile id."""
+    the stable permutation that groups particles by tile id.  A local
+    coordinate that rounds onto the upper tile face moves to the next tile at
+    -T/2; with walls in x, one that would cross the wall at x = n0 stays in
+    the last tile just below the face instead."""
     x = np.asarray(x, dtype=np.float64)
     npart = x.shape[1]
     nt = tile_grid(n, T, D)
@@ -54,8 +58,11 @@ def bin_global(x, n, T, D, dtype):
         loc = (x[d] - centre.astype(np.float64)).astype(dtype)
         half = dtype(T[d] // 2)
         up = loc >= half
-        t = np.where(up, (t + 1) % nt[d], t)
-        loc = np.where(up, -half, loc).astype(dtype)
+        stay = up & (d == 0) & walls & (t == nt[d] - 1)
+        move = up & ~stay
+        t = np.where(move, (t + 1) % nt[d], t)
+        loc = np.where(move, -half, loc).astype(dtype)
+        loc = np.where(stay, np.nextafter(half, dtype(0)), loc).astype(dtype)
         tc[d] = t
         xl[d] = loc
     tid = tile_linear(tc, nt)

@@ -30,6 +30,7 @@ PIC_PUSH_HALF_B = 4
 PIC_OPT_ACC_WORKING = 1
 PIC_OPT_PERSISTENT = 2
 PIC_OPT_TRACK = 4
+PIC_WALL_X = 1
 
 EXPORTS = ["pic_query", "pic_init_tiles", "pic_fdtd_step", "pic_push_interp", "pic_deposit_current",
            "pic_sort_migrate", "pic_step", "pic_graph_capture", "pic_graph_launch", "pic_error",
@@ -48,7 +49,7 @@ class PicConfig(ctypes.Structure):
         ("dim", I32), ("precision", I32), ("n_species", I32), ("n_boxes", I32),
         ("tile", I32 * 3), ("block", I32), ("cfl", DBL),
         ("box_cells", P), ("charge", P), ("qm", P), ("mass", P), ("tile_capacity", P),
-        ("capacity_factor", DBL), ("outbox_capacity", I32), ("options", U32),
+        ("capacity_factor", DBL), ("outbox_capacity", I32), ("options", U32), ("box_walls", P),
     ]
 
 

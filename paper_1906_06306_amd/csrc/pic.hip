@@ -127,6 +127,8 @@ pic_status make_layout(const pic_config *c, const int64_t *counts, Layout &L)
                     for (int d = 0; d < 3; ++d) td.nt[d] = nt[d], td.n[d] = n[d];
                     td.cell0 = cells;
                     td.tile0 = (int32_t)tiles;
+                    if (c->box_walls && (c->box_walls[b] & PIC_WALL_X))
+                        td.walls = (tx == 0 ? 1 : 0) | (tx == nt[0] - 1 ? 2 : 0);
                     L.tiles.push_back(td);
                 }
         cells += (int64_t)n[0] * n[1] * n[2];
@@ -248,6 +250,7 @@ struct pic_ctx {
     bool acc_working;   // LDS current block in the working precision
     bool persistent;    // push as a persistent tile walker
     bool track;         // origin tracking and adjoint scratch present
+    bool walls;         // some box has conducting walls in x
     int n_cu;           // compute units of the device
     hipGraphExec_t graph;   // captured steps, or null
     int graph_steps;
@@ -356,14 +359,14 @@ struct Impl {
         return PIC_OK;
     }
 
-    template <bool FUSED, bool HALFB, typename A, int TC>
+    template <bool FUSED, bool HALFB, typename A, int TC, bool WALLS>
     static pic_status push_launch(pic_ctx *x)
     {
         Params<R> p = params<R>(x);
         size_t lds = push_lds(x, FUSED, sizeof(A));
         dim3 b(x->block);
         if (x->persistent) {
-            auto kern = pic::k_push_persistent<R, D, FUSED, HALFB, A, PUSH_UNROLL, TC>;
+            auto kern = pic::k_push_persistent<R, D, FUSED, HALFB, A, PUSH_UNROLL, TC, WALLS>;
             pic_status st = set_lds(kern, lds);
             if (st) return st;
             int per_cu = 0;
@@ -374,7 +377,7 @@ struct Impl {
             if (st) return st;
             hipLaunchKernelGGL(kern, dim3((unsigned)grid), b, lds, x->stream, p);
         } else {
-            auto kern = pic::k_push<R, D, FUSED, HALFB, A, PUSH_UNROLL, TC>;
+            auto kern = pic::k_push<R, D, FUSED, HALFB, A, PUSH_UNROLL, TC, WALLS>;
             pic_status st = set_lds(kern, lds);
             if (st) return st;
             hipLaunchKernelGGL(kern, dim3((unsigned)x->L.pub.tiles_total), b, lds, x->stream, p);
@@ -389,15 +392,18 @@ struct Impl {
     template <bool FUSED, bool HALFB, typename A>
     static pic_status push_with(pic_ctx *x)
     {
+        if constexpr (FUSED) {
+            if (x->walls) return push_launch<FUSED, HALFB, A, 0, true>(x);
+        }
         if constexpr (FUSED && std::is_same<A, double>::value) {
             bool cubic = true;
             for (int d = 1; d < D; ++d) cubic = cubic && x->T[d] == x->T[0];
-            if (cubic && x->T[0] == 8) return push_launch<FUSED, HALFB, A, 8>(x);
-            if (cubic && x->T[0] == 16) return push_launch<FUSED, HALFB, A, 16>(x);
+            if (cubic && x->T[0] == 8) return push_launch<FUSED, HALFB, A, 8, false>(x);
+            if (cubic && x->T[0] == 16) return push_launch<FUSED, HALFB, A, 16, false>(x);
             if constexpr (D < 3)
-                if (cubic && x->T[0] == 32) return push_launch<FUSED, HALFB, A, 32>(x);
+                if (cubic && x->T[0] == 32) return push_launch<FUSED, HALFB, A, 32, false>(x);
         }
-        return push_launch<FUSED, HALFB, A, 0>(x);
+        return push_launch<FUSED, HALFB, A, 0, false>(x);
     }
 
     static pic_status push(pic_ctx *x, bool fused, bool halfb)
@@ -499,6 +505,7 @@ struct Impl {
                 g.nchunks = (int32_t)std::min<int64_t>(L.nchunks_max, std::max<int64_t>(1, (count + 4095) / 4096));
                 g.chunk = (int32_t)((count + g.nchunks - 1) / g.nchunks);
                 g.id_base = id_base - count;
+                g.walls = L.tiles[L.box_tile0[b]].walls != 0 || L.tiles[L.box_tile0[b] + t0.nt[0] - 1].walls != 0;
                 int kgrid = (int)std::min<int64_t>((count + 255) / 256, 16384);
                 hipLaunchKernelGGL((pic::k_bin_keys<R, D>), dim3(kgrid), dim3(256), 0, x->stream, g, in->pos[b * x->ns + s],
                                    key, xl, p.err, p.nearface);
@@ -514,6 +521,10 @@ struct Impl {
                                    in->u[b * x->ns + s], hist, p, (int)L.box_tile0[b], s);
                 HIP_OK(hipGetLastError());
             }
+        }
+        if (x->walls) {
+            hipLaunchKernelGGL((pic::k_hold_walls<R, D>), dim3((unsigned)L.pub.tiles_total), dim3(256), 0, x->stream, p);
+            HIP_OK(hipGetLastError());
         }
         return PIC_OK;
     }
@@ -712,6 +723,8 @@ pic_status pic_init_tiles(const pic_config *cfg, const int64_t *counts, void *wo
     x->acc_working = (cfg->options & PIC_OPT_ACC_WORKING) != 0;
     x->persistent = (cfg->options & PIC_OPT_PERSISTENT) != 0;
     x->track = (cfg->options & PIC_OPT_TRACK) != 0;
+    x->walls = false;
+    for (int b = 0; cfg->box_walls && b < cfg->n_boxes; ++b) x->walls = x->walls || (cfg->box_walls[b] & PIC_WALL_X);
     x->graph = nullptr;
     x->graph_steps = 0;
     {
@@ -770,6 +783,7 @@ pic_status pic_push_interp(pic_ctx *x, uint32_t flags)
     if (x->state != 0) return fail(PIC_E_STATE, "push called before the previous push was deposited and migrated");
     const bool fused = flags & PIC_FUSED;
     if (x->track && !fused) return fail(PIC_E_ARG, "origin tracking records origins in the fused push only");
+    if (x->walls && !fused) return fail(PIC_E_ARG, "boxes with walls need the fused push (PIC_FUSED)");
     pic_status st = do_push(x, fused, (flags & PIC_PUSH_HALF_B) != 0);
     if (st) return st;
     x->state = fused ? 2 : 1;
@@ -898,6 +912,7 @@ pic_status pic_adjoint_step(pic_ctx *x, void *lpos, void *lu, void *lE, void *lB
 {
     if (!x) return fail(PIC_E_ARG, "null context");
     if (!x->track) return fail(PIC_E_STATE, "the context was created without PIC_OPT_TRACK");
+    if (x->walls) return fail(PIC_E_ARG, "the adjoint step covers periodic boxes only");
     if (!lpos || !lu || !lE || !lB) return fail(PIC_E_ARG, "adjoint buffers are required");
     if (x->state != 0) return fail(PIC_E_STATE, "the adjoint step must start between steps");
     return do_adjoint(x, lpos, lu, lE, lB);

@@ -34,6 +34,7 @@ struct BinGeom {
     int32_t nchunks;
     int32_t chunk;        // particles per chunk
     int64_t id_base;      // origin id of input particle 0 of this (box, species)
+    int32_t walls;        // the box has conducting walls at x = 0 and x = n0
 };
 
 template <typename R>
@@ -64,8 +65,12 @@ __global__ void k_bin_keys(BinGeom g, const double *pos, int32_t *key, R *xl, in
             R loc = (R)(x - centre);
             const R half = R(g.T[d] / 2);
             if (loc >= half) {
-                t = t + 1 == g.nt[d] ? 0 : t + 1;
-                loc = -half;
+                if (d == 0 && g.walls && t + 1 == g.nt[0]) {
+                    loc = nextafter(half, R(0));   // stays below the wall at x = n0
+                } else {
+                    t = t + 1 == g.nt[d] ? 0 : t + 1;
+                    loc = -half;
+                }
             }
             tc[d] = t;
             xl[d * g.count + i] = loc;
@@ -80,6 +85,24 @@ __global__ void k_bin_keys(BinGeom g, const double *pos, int32_t *key, R *xl, in
         nf += flag;
     }
     if (nf) atomicAdd(nearface, nf);
+}
+
+// Zero the wall planes (Ey, Ez, Bx at x = 0) of the tiles on a low-x wall.
+template <typename R, int D>
+__global__ void __launch_bounds__(256) k_hold_walls(Params<R> p)
+{
+    const TileDesc td = p.tiles[blockIdx.x];
+    if (!(td.walls & 1)) return;
+    const int T1 = D > 1 ? p.T[1] : 1, T2 = D > 2 ? p.T[2] : 1;
+    const int64_t N = p.cells_total;
+    for (int k = threadIdx.x; k < T1 * T2; k += blockDim.x) {
+        const int gy = D > 1 ? td.tc[1] * T1 + k % T1 : 0;
+        const int gz = D > 2 ? td.tc[2] * T2 + k / T1 : 0;
+        const int64_t g = td.cell0 + (int64_t)td.n[0] * (gy + (int64_t)td.n[1] * gz);
+        p.E[N + g] = R(0);
+        p.E[2 * N + g] = R(0);
+        p.B[g] = R(0);
+    }
 }
 
 // Per-chunk tile histograms.
@@ -329,7 +352,8 @@ __global__ void __launch_bounds__(256) k_diag_gauss(Params<R> p, double *part, c
         const int64_t km = at(gx, gy, gz == 0 ? td.n[2] - 1 : gz - 1);
         double dive = ((double)p.E[g] - (double)p.E[im]) + ((double)p.E[N + g] - (double)p.E[N + jm]) +
                       ((double)p.E[2 * N + g] - (double)p.E[2 * N + km]);
-        gmax = fmax(gmax, fabs(dive - rho));
+        // the wall plane carries the conductor's surface charge: no Gauss law there
+        if (!((td.walls & 1) && gx == 0)) gmax = fmax(gmax, fabs(dive - rho));
         qsum += rho;
     }
     double m = wg_max(gmax, red);

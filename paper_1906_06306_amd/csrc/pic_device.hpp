@@ -22,7 +22,8 @@ struct TileDesc {
     int32_t n[3];       // cells per dimension of the box
     int64_t cell0;      // offset of the box's first cell in the field planes
     int32_t tile0;      // global id of the box's tile (0,0,0)
-    int32_t pad;
+    int32_t walls;      // bit 0: conducting wall on the tile's low-x face
+                        // (x = 0), bit 1: on its high-x face (x = n0)
 };
 
 // Launch-wide constants of the particle and field kernels.
@@ -442,6 +443,77 @@ __device__ __forceinline__ void zigzag(A *sJ, const CurBox<D> &cb, const int32_t
 #pragma unroll
         for (int k = 0; k < NV; ++k) lds_add(sJ + b2 + seg_offset<D>(cb, k), v2[k]);
     }
+}
+
+// ------------------------------------------------------------------ walls
+
+// Conducting, reflecting walls at x = 0 and x = n0 (y, z periodic): the
+// x-staggered components (Ex, By, Bz) see the wall as a mirror, the
+// node-centred ones (Ey, Ez, Bx) vanish on the wall plane.  Applied to the
+// staged LDS blocks of a wall tile after push_half_b1: the low wall's ghost
+// column (local x = -1) and the high wall's column (local x = T) take the
+// image values.
+template <typename R, int D>
+__device__ __forceinline__ void wall_images(R *sE, const CurBox<D> &cb, R *sB, const FieldBox<D> &fb,
+                                            const int32_t T[3], int walls)
+{
+    const int rows_e = cb.e1 * cb.e2, rows_b = fb.e1 * fb.e2;
+    for (int r = threadIdx.x; r < rows_e; r += blockDim.x) {
+        R *row = sE + r * cb.e0;
+        if (walls & 1) row[0] = row[1];                         // Ex(-1/2) = Ex(1/2)
+        if (walls & 2) {
+            row[T[0] + 1] = row[T[0]];                          // Ex(n0+1/2) = Ex(n0-1/2)
+            row[cb.n + T[0] + 1] = R(0);                        // Ey, Ez on the wall plane
+            row[2 * cb.n + T[0] + 1] = R(0);
+        }
+    }
+    for (int r = threadIdx.x; r < rows_b; r += blockDim.x) {
+        R *row = sB + r * fb.e0;
+        if (walls & 1) {
+            row[fb.n] = row[fb.n + 1];                          // By, Bz mirror
+            row[2 * fb.n] = row[2 * fb.n + 1];
+        }
+        if (walls & 2) {
+            row[T[0] + 1] = R(0);                               // Bx on the wall plane
+            row[fb.n + T[0] + 1] = row[fb.n + T[0]];
+            row[2 * fb.n + T[0] + 1] = row[2 * fb.n + T[0]];
+        }
+    }
+}
+
+// A particle of a wall tile whose move ends beyond the wall is reflected:
+// the current runs along the broken path x1 -> wall point -> mirrored end
+// (two ZigZag moves, the non-grid displacement split in proportion), then
+// x2 and u_x are mirrored.  Returns false (nothing done) for other moves.
+template <typename R, int D, typename A>
+__device__ __forceinline__ bool wall_reflect(A *sJ, const CurBox<D> &cb, const int32_t T[3], int walls,
+                                             const R x1[3], R x2[3], R u[3], const R dv[3], R q)
+{
+    const R half = R(T[0] / 2);
+    const bool lo = (walls & 1) && x2[0] < -half;
+    const bool hi = (walls & 2) && x2[0] >= half;
+    if (!(lo || hi)) return false;
+    const R wx = lo ? -half : half;
+    const R t = (wx - x1[0]) / (x2[0] - x1[0]);
+    R w[3] = {wx, 0, 0}, r[3] = {0, 0, 0}, dv1[3] = {0, 0, 0}, dv2[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 1; d < 3; ++d) {
+        if (d < D) {
+            w[d] = x1[d] + t * (x2[d] - x1[d]);
+            r[d] = x2[d];
+        } else {
+            dv1[d] = t * dv[d];
+            dv2[d] = dv[d] - dv1[d];
+        }
+    }
+    r[0] = lo ? -R(T[0]) - x2[0] : R(T[0]) - x2[0];
+    if (r[0] >= half) r[0] = nextafter(half, R(0));
+    zigzag<R, D, A>(sJ, cb, T, x1, w, dv1, q);
+    zigzag<R, D, A>(sJ, cb, T, w, r, dv2, q);
+#pragma unroll
+    for (int d = 0; d < D; ++d) x2[d] = r[d];
+    u[0] = -u[0];
+    return true;
 }
 
 // Tile offset code sum (delta_d+1) 3^d of a position after the push.

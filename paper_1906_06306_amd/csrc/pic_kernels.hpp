@@ -142,7 +142,7 @@ __device__ __forceinline__ void compact_chunk(const Params<R> &p, int ts, int64_
 // c0 + j*blockDim + t), so every load and store instruction stays
 // coalesced while U loads per array are in flight; the stable compaction
 // runs once per group.
-template <typename R, int D, bool FUSED, bool HALFB, typename A, int U, int TC>
+template <typename R, int D, bool FUSED, bool HALFB, typename A, int U, int TC, bool WALLS>
 __device__ __forceinline__ void push_tile(const Params<R> &p, const int t, unsigned char *smem)
 {
     const TileDesc td = p.tiles[t];
@@ -173,6 +173,12 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int t, unsig
     if constexpr (HALFB) {
         half_b_lds<R, D>(sB, fb, sE, cb, R(0.5) * p.c);
         __syncthreads();
+    }
+    if constexpr (WALLS) {
+        if (td.walls) {
+            wall_images<R, D>(sE, cb, sB, fb, T, td.walls);
+            __syncthreads();
+        }
     }
     const R c = p.c, inv_c = p.inv_c;
     const int64_t cap = p.cap_total;
@@ -251,7 +257,9 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int t, unsig
                     for (int d = 0; d < D; ++d) x2[j][d] = x[j][d] + dv[d];
                     if (finite3<R>(u[j]) && moved_ok<R, D>(x2[j], dv, T)) {
                         if constexpr (FUSED) {
-                            zigzag<R, D, A>(sJ, cb, T, x[j], x2[j], dv, q);
+                            bool done = false;
+                            if constexpr (WALLS) done = wall_reflect<R, D, A>(sJ, cb, T, td.walls, x[j], x2[j], u[j], dv, q);
+                            if (!done) zigzag<R, D, A>(sJ, cb, T, x[j], x2[j], dv, q);
                             code[j] = direction_code<R, D>(x2[j], T, delta[j]);
                         }
                     } else {
@@ -351,17 +359,17 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int t, unsig
 }
 
 // One work-group per tile, tiles dispatched heaviest first.
-template <typename R, int D, bool FUSED, bool HALFB, typename A, int U, int TC>
+template <typename R, int D, bool FUSED, bool HALFB, typename A, int U, int TC, bool WALLS>
 __global__ void __launch_bounds__(1024) k_push(Params<R> p)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    push_tile<R, D, FUSED, HALFB, A, U, TC>(p, p.order[blockIdx.x], smem);
+    push_tile<R, D, FUSED, HALFB, A, U, TC, WALLS>(p, p.order[blockIdx.x], smem);
 }
 
 // Persistent tile walker: a grid sized to the resident work-groups pulls
 // tiles (heaviest first) from an atomic counter until every tile is taken;
 // every work-group leaves the loop when the counter passes the tile count.
-template <typename R, int D, bool FUSED, bool HALFB, typename A, int U, int TC>
+template <typename R, int D, bool FUSED, bool HALFB, typename A, int U, int TC, bool WALLS>
 __global__ void __launch_bounds__(1024) k_push_persistent(Params<R> p)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -372,7 +380,7 @@ __global__ void __launch_bounds__(1024) k_push_persistent(Params<R> p)
         const int k = next;
         __syncthreads();
         if (k >= p.ntiles) break;
-        push_tile<R, D, FUSED, HALFB, A, U, TC>(p, p.order[k], smem);
+        push_tile<R, D, FUSED, HALFB, A, U, TC, WALLS>(p, p.order[k], smem);
         __syncthreads();
     }
 }
@@ -504,9 +512,10 @@ __global__ void __launch_bounds__(256) k_field(Params<R> p, R h)
             p.B[N + g] = by;
             p.B[2 * N + g] = bz;
         } else if constexpr (PHASE == 2) {
+            const bool wall = (td.walls & 1) && gx == 0;
             p.E[g] -= p.J[g];
-            p.E[N + g] -= p.J[N + g];
-            p.E[2 * N + g] -= p.J[2 * N + g];
+            p.E[N + g] = wall ? R(0) : p.E[N + g] - p.J[N + g];
+            p.E[2 * N + g] = wall ? R(0) : p.E[2 * N + g] - p.J[2 * N + g];
         } else {
             const R *Bx = p.B, *By = p.B + N, *Bz = p.B + 2 * N;
             const int64_t im = D > 0 ? at(gx == 0 ? n0 - 1 : gx - 1, gy, gz) : g;
@@ -522,6 +531,7 @@ __global__ void __launch_bounds__(256) k_field(Params<R> p, R h)
                 ey -= p.J[N + g];
                 ez -= p.J[2 * N + g];
             }
+            if ((td.walls & 1) && gx == 0) ey = ez = R(0);   // tangential E on the wall plane
             p.E[g] = ex;
             p.E[N + g] = ey;
             p.E[2 * N + g] = ez;

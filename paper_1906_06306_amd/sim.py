@@ -45,7 +45,7 @@ class PicSim:
 
     def __init__(self, boxes, tile, precision: str = "fp32", block: int = 256, capacity_factor: float = 1.25,
                  tile_capacity=None, outbox_capacity: int = 0, options: int = 0, device: str = "cuda:0",
-                 stream=None):
+                 stream=None, walls=False):
         if not isinstance(boxes, (list, tuple)):
             boxes = [boxes]
         boxes = [b if isinstance(b, Box) else box_from_plasma(b) for b in boxes]
@@ -87,6 +87,9 @@ class PicSim:
         cfg.capacity_factor = capacity_factor
         cfg.outbox_capacity = outbox_capacity
         cfg.options = options
+        wl = walls if isinstance(walls, (list, tuple)) else [walls] * self.nb
+        self._walls = np.array([L.PIC_WALL_X if w else 0 for w in wl], dtype=np.int32)
+        cfg.box_walls = self._walls.ctypes.data if self._walls.any() else None
         self.cfg = cfg
         lay = L.PicLayout()
         L.check(lib.pic_query(ctypes.byref(cfg), self._counts.ctypes.data, ctypes.byref(lay)))

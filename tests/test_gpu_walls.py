@@ -1,0 +1,161 @@
+"""GPU conducting, reflecting walls in x against the oracle's wall step.
+
+* One fused step from a common state of a hot plasma that hits both walls:
+  E, B, J within 1e-12 (FP64) / 1e-5 (FP32) relative L2 of the oracle; every
+  particle (matched through the origin ids) at the oracle's position and
+  momentum, reflected ones included.
+* The vacuum standing wave between the walls follows the closed form of the
+  discrete lattice.
+* Over many steps Gauss's residual stays constant at every node off the wall
+  plane and every particle stays inside the box.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import tiles
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def make_sim(plasma, T, prec, **kw):
+    from paper_1906_06306_amd.sim import PicSim
+    print(f"[gpu] walled PicSim D={plasma.D} n={plasma.n} T={T} prec={prec} np={plasma.nparticles}", flush=True)
+    return PicSim(plasma, tile=T, precision=prec, walls=True, capacity_factor=2.0, **kw)
+
+
+def slots_in_order(sim, species):
+    """Segment slot of every particle, in particles_host order."""
+    _, _, _, off, cnt = sim.particle_views()
+    off, cnt = off.cpu().numpy(), cnt.cpu().numpy()
+    return np.concatenate([np.arange(off[t, species], off[t, species] + cnt[t, species])
+                           for t in range(off.shape[0])])
+
+
+def common_state(sim, plasma):
+    st = oracle.State(plasma)
+    E, B, _ = sim.fields_host(0)
+    st.E[:] = E
+    st.B[:] = B
+    for s in range(len(plasma.species)):
+        tid, xl, u = sim.particles_host(0, s)
+        st.x[s] = np.ascontiguousarray(tiles.to_global(tid, xl, plasma.n, sim.T, plasma.D))
+        st.u[s] = np.ascontiguousarray(u.astype(np.float64))
+    return st
+
+
+CASES = [
+    (1, (64, 1, 1), (16, 1, 1), 16),
+    (2, (32, 16, 1), (8, 8, 1), 4),
+    (3, (16, 8, 8), (8, 4, 4), 2),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("D,n,T,ppc", CASES)
+def test_walls_fused_step_matches_oracle(D, n, T, ppc, prec):
+    from paper_1906_06306_amd import _lib as L
+    plasma = synth.small_random(D, n, ppc, theta=2.0, seed=61 + D, field_amp=0.05, q=0.01)
+    sim = make_sim(plasma, T, prec, options=L.PIC_OPT_TRACK)
+    st = common_state(sim, plasma)
+    st.hold_walls()
+    common_x = [x.copy() for x in st.x]
+    pre = [slots_in_order(sim, s) for s in range(2)]
+    sim.step(1, fused=True, half_b_in_push=True)
+    st.step(1, walls=True)
+    assert sim.error() == 0
+    tol = TOL[prec]
+    E, B, J = sim.fields_host(0)
+    assert rel(J, st.J) < tol, rel(J, st.J)
+    assert rel(B, st.B) < tol and rel(E, st.E) < tol, (rel(B, st.B), rel(E, st.E))
+    ids = sim.ids_host()
+    reflected = 0
+    for s in range(2):
+        # the oracle's reflected particles: not at the free end point
+        g = np.sqrt(1.0 + (st.u[s] ** 2).sum(axis=0))
+        free = common_x[s][0] + plasma.c * st.u[s][0] / g
+        reflected += int((np.abs(st.x[s][0] - free) > 1e-9).sum())
+        tid, xl, u = sim.particles_host(0, s)
+        gx = tiles.to_global(tid, xl, n, T, D)
+        origin = ids[slots_in_order(sim, s)]
+        k = np.searchsorted(pre[s], origin)
+        assert np.array_equal(pre[s][k], origin)
+        ptol = 1e-12 if prec == "fp64" else 4e-6 * max(T)
+        assert np.abs(gx - st.x[s][:, k]).max() < ptol
+        assert rel(u.astype(np.float64), st.u[s][:, k]) < tol * 10
+        assert gx[0].min() >= 0.0 and gx[0].max() < n[0]
+    assert reflected > 0, "no particle reached a wall"
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("D,n,T", [(1, (32, 1, 1), (8, 1, 1)), (2, (24, 8, 1), (8, 8, 1))])
+def test_walls_standing_wave(D, n, T, prec):
+    p = synth.small_random(D, n, 1, seed=1)
+    for sp in p.species:
+        sp.x = sp.x[:, :0].copy()
+        sp.u = sp.u[:, :0].copy()
+    N = int(np.prod(n))
+    i = np.arange(N) % n[0]
+    k = 3 * math.pi / n[0]
+    c = p.c
+    w = 2.0 * math.asin(c * math.sin(0.5 * k))
+    p.E[:] = 0.0
+    p.B[:] = 0.0
+    p.E[1] = np.sin(k * i)
+    p.B[2] = math.sin(0.5 * w) * np.cos(k * (i + 0.5))
+    sim = make_sim(p, T, prec)
+    nsteps = 37
+    sim.step(nsteps, fused=True, half_b_in_push=True)
+    E, B, _ = sim.fields_host(0)
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    assert np.abs(E[1] - np.sin(k * i) * math.cos(w * nsteps)).max() < tol
+    assert np.abs(B[2] + np.cos(k * (i + 0.5)) * math.sin(w * (nsteps - 0.5))).max() < tol
+    sim.close()
+
+
+@pytest.mark.parametrize("D,n,T,ppc", CASES)
+def test_walls_charge_conservation_many_steps(D, n, T, ppc):
+    """FP64, 40 steps: div E - rho unchanged off the wall plane."""
+    plasma = synth.small_random(D, n, ppc, theta=2.0, seed=71 + D, field_amp=0.0, q=0.01)
+    sim = make_sim(plasma, T, "fp64")
+
+    def residual():
+        st = common_state(sim, plasma)
+        return st.gauss_residual()
+    r0 = residual()
+    sim.step(40, fused=True, half_b_in_push=True)
+    assert sim.error() == 0
+    r = residual()
+    N = int(np.prod(n))
+    interior = (np.arange(N) % n[0]) != 0
+    assert np.abs(r - r0)[interior].max() < 1e-12
+    for s in range(2):
+        tid, xl, u = sim.particles_host(0, s)
+        gx = tiles.to_global(tid, xl, n, T, D)
+        assert gx[0].min() >= 0.0 and gx[0].max() < n[0]
+    d = sim.diagnostics()
+    assert d["status"] == 0 and d["particles"] == plasma.nparticles
+    sim.close()
+
+
+def test_walls_reject_unfused_and_adjoint():
+    from paper_1906_06306_amd import _lib as L
+    plasma = synth.small_random(2, (16, 16), 2, seed=3)
+    sim = make_sim(plasma, (8, 8), "fp64", options=L.PIC_OPT_TRACK)
+    assert L.lib().pic_push_interp(sim.ctx, 0) == L.PIC_E_ARG
+    la, ua, lE, lB = sim.adjoint_buffers()
+    assert L.lib().pic_adjoint_step(sim.ctx, la.data_ptr(), ua.data_ptr(), lE.data_ptr(), lB.data_ptr()) \
+        == L.PIC_E_ARG
+    sim.close()
