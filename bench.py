@@ -54,10 +54,11 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps timed for the CPU baseline")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale rocprofv3 FETCH/WRITE_SIZE)")
-    ap.add_argument("--workload", default="turbulence", choices=["turbulence", "shear-adjoint"],
+    ap.add_argument("--workload", default="turbulence", choices=["turbulence", "shear-adjoint", "shock"],
                     help="turbulence: the throughput line; shear-adjoint: the differentiable window "
                          "(256^2, 32 ppc/species, 40 steps, checkpoints every 8) with its forward and "
-                         "reverse rates and gradients")
+                         "reverse rates and gradients; shock: 3D3V pre-shocked plasma between walls, "
+                         "1024x128x128, 4:1 uneven tiles, per-tile and persistent push")
     ap.add_argument("--fd", action="store_true", help="shear-adjoint: also central differences of the FP64 forward")
     return ap.parse_args()
 
@@ -231,6 +232,76 @@ def bench_adjoint(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_shock(args):
+    """3D3V pre-shocked pair plasma between conducting walls in x: 1024 x
+    128 x 128 cells, 8^3 tiles, 32 ppc/species downstream (x < 256) and 8
+    upstream (469.8 M particles), FP32, per-tile push and persistent tile
+    walker.  One JSON line (not the headline metric)."""
+    import torch
+    import synth
+    from paper_1906_06306_amd import _lib as L
+    from paper_1906_06306_amd.sim import PicSim
+
+    t0 = time.perf_counter()
+    plasma = synth.shock(log=log)
+    n_p, n_c, D = plasma.nparticles, plasma.ncells, 3
+    T = (8, 8, 8)
+    log(f"generated {n_p} particles in {time.perf_counter() - t0:.1f}s")
+    results = {}
+    for name, opts in (("per_tile", 0), ("persistent", L.PIC_OPT_PERSISTENT)):
+        # segment capacities from the initial per-tile counts (4:1 uneven)
+        sim = PicSim(plasma, tile=T, precision="fp32", tile_capacity="auto", capacity_factor=1.25, options=opts,
+                     walls=True)
+        log(f"{name}: initialised")
+        stream = torch.cuda.current_stream()
+        lib = L.lib()
+        flags = L.PIC_FUSED | L.PIC_PUSH_HALF_B
+        for _ in range(args.warmup):
+            L.check(lib.pic_step(sim.ctx, flags))
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        t1 = time.perf_counter()
+        for k in range(args.steps):
+            evs[k][0].record(stream)
+            L.check(lib.pic_push_interp(sim.ctx, flags))
+            evs[k][1].record(stream)
+            L.check(lib.pic_fdtd_step(sim.ctx, L.PIC_TWO_HALF_B))
+            L.check(lib.pic_deposit_current(sim.ctx, flags))
+            L.check(lib.pic_fdtd_step(sim.ctx, L.PIC_CURL_E_ADD_J))
+            L.check(lib.pic_sort_migrate(sim.ctx, 0))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        push_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        diag = sim.diagnostics()
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        results[name] = dict(seconds=dt, push_ms=push_ms, diag=diag)
+        log(f"{name}: {dt / args.steps * 1e3:.3f} ms/step, push {push_ms:.3f} ms, status {diag['status']}")
+    best = min(results, key=lambda k: results[k]["seconds"])
+    r = results[best]
+    value = n_p * args.steps / r["seconds"]
+    pb = push_bytes(D, 4, n_p, n_c)
+    achieved = pb / (r["push_ms"] * 1e-3) / 1e9
+    out = {
+        "metric": "particle-steps/s (push+deposit+FDTD) FP32 at 1 GPU, 3D shock between walls",
+        "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": r["seconds"] / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "3D3V pre-shocked pair plasma 1024x128x128, conducting walls in x, "
+                               "x<256: 32 ppc/species theta=3.286; x>=256: 8 ppc/species beam gamma=10",
+                   "particles": n_p, "cells": n_c, "tile": list(T), "push": best},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_push<float,3,fused,walls>",
+                     "push_ms": r["push_ms"], "algorithmic_bytes_per_launch": pb},
+        "step_roofline_frac": algorithmic_bytes(D, 4, n_p, n_c) * value / n_p / 1e9 / HBM_PEAK_GBS,
+        "per_tile_ms_per_step": results["per_tile"]["seconds"] / args.steps * 1e3,
+        "persistent_ms_per_step": results["persistent"]["seconds"] / args.steps * 1e3,
+        "status": {k: v["diag"]["status"] for k, v in results.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -246,6 +317,9 @@ def main():
         return
     if args.workload == "shear-adjoint":
         bench_adjoint(args)
+        return
+    if args.workload == "shock":
+        bench_shock(args)
         return
     t0 = time.perf_counter()
     plasma = synth.turbulence(n=args.n, ppc=args.ppc)

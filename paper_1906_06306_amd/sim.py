@@ -69,6 +69,8 @@ class PicSim:
         self._qm = np.array([b.qm for b in boxes], dtype=np.float64)
         self._mass = np.array([b.mass for b in boxes], dtype=np.float64)
         self._counts = np.array([[int(p.shape[1]) for p in b.pos] for b in boxes], dtype=np.int64)
+        if isinstance(tile_capacity, str) and tile_capacity == "auto":
+            tile_capacity = self._capacity_from_counts(boxes, tile, capacity_factor)
         self._tcap = None if tile_capacity is None else np.ascontiguousarray(tile_capacity, dtype=np.int64)
         cfg = L.PicConfig()
         cfg.dim = self.D
@@ -132,6 +134,33 @@ class PicSim:
         self.nt = [[b.n[d] // self.T[d] if d < self.D else 1 for d in range(3)] for b in boxes]
         self.tile0 = np.cumsum([0] + [int(np.prod(nt)) for nt in self.nt])[:-1]
         self.cell0 = np.cumsum([0] + [int(np.prod(c)) for c in self._cells])[:-1]
+
+    def _capacity_from_counts(self, boxes, tile, factor):
+        """Segment capacities [tiles][species] from the initial particles of
+        every tile (uneven loads): ceil(factor * c) + 64, where c is the
+        largest count among the tile and its neighbours (a front between a
+        dense and a thin region moves into the thin tiles)."""
+        T = tuple(int(t) for t in tile) + (1,) * (3 - len(tile))
+        out = []
+        for b in boxes:
+            n = list(b.n) + [1] * (3 - len(b.n))
+            nt = [n[d] // T[d] for d in range(3)]
+            cols = []
+            for pos in b.pos:
+                x = pos.detach().cpu().numpy() if isinstance(pos, torch.Tensor) else np.asarray(pos)
+                tid = np.zeros(x.shape[1], dtype=np.int64)
+                stride = 1
+                for d in range(self.D):
+                    tid += np.clip(np.floor(x[d] / T[d]).astype(np.int64), 0, nt[d] - 1) * stride
+                    stride *= nt[d]
+                cnt = np.bincount(tid, minlength=nt[0] * nt[1] * nt[2]).reshape(nt[2], nt[1], nt[0])
+                big = cnt.copy()
+                for ax in range(3):
+                    if nt[2 - ax] > 1:
+                        big = np.maximum(big, np.maximum(np.roll(big, 1, axis=ax), np.roll(big, -1, axis=ax)))
+                cols.append(big.reshape(-1))
+            out.append(np.stack(cols, axis=1))
+        return np.ceil(np.concatenate(out, axis=0) * factor).astype(np.int64) + 64
 
     # ------------------------------------------------------------ calls
     def fdtd(self, phase: int):

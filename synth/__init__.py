@@ -12,6 +12,8 @@ Workloads (all self-initialised from formulas; the paper uses no dataset):
 * ``turbulence``  - 2D3V decaying magnetised turbulence (Sect. 5.3): warm
                     Maxwell-Juttner pair plasma, guide field B0 z from the
                     magnetisation sigma, 64 random-phase forcing modes.
+* ``shock``       - 3D3V pre-shocked pair plasma between conducting walls
+                    (Sect. 5.2): hot dense downstream, cold upstream beam.
 * ``ensemble``    - many small independent 2D3V thermal boxes.
 * ``shear``       - 2D3V magnetised plasma with a sinusoidal shear drift,
                     the differentiable-window workload.
@@ -244,6 +246,45 @@ def turbulence(n: int = 1024, ppc: int = 16, theta: float = 0.3, sigma: float = 
     meta = dict(workload="turbulence", ppc=ppc, theta=theta, sigma=sigma, Rp=Rp,
                 mean_gamma=mg, B0=B0, dB=dB_over_B0 * B0)
     return _pair(2, dims, c, qabs, x, ue, x.copy(), up, E, B, meta)
+
+
+def shock(n: tuple = (1024, 128, 128), x_shock: int = 256, ppc_down: int = 32, ppc_up: int = 8,
+          theta_down: float = 3.286, gamma_up: float = 10.0, theta_up: float = 1e-4, Rp: float = 10.0,
+          c: float = 0.45, seed: int = BASE_SEED + 3, log=None) -> Plasma:
+    """3D3V pre-shocked pair plasma between conducting walls in x (Sect. 5.2
+    setup, started from a shocked state): for x < x_shock a hot plasma at
+    rest (Maxwell-Juttner theta_down, ppc_down per species, mean Lorentz
+    factor equal to the upstream gamma_up), for x >= x_shock the cold
+    upstream beam moving towards the wall at x = 0 (Lorentz factor
+    gamma_up, theta_up boosted, ppc_up per species).  |q| follows the
+    upstream (ppc_up, <gamma> = gamma_up); E = B = 0.  Each positron sits
+    on an electron (zero charge density at the start)."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = n
+    down = quiet_positions(rng, 3, (x_shock, ny, nz), ppc_down)
+    up = quiet_positions(rng, 3, (nx - x_shock, ny, nz), ppc_up)
+    up[0] += x_shock
+    x = np.concatenate([down, up], axis=1)
+    del down, up
+    if log:
+        log(f"shock: {x.shape[1]} positions per species")
+    nd = ppc_down * x_shock * ny * nz
+    nu = x.shape[1] - nd
+    us = []
+    for k in range(2):
+        u = np.empty((3, nd + nu))
+        u[:, :nd] = sample_mj(rng, theta_down, nd)
+        u[:, nd:] = boost_x(rng, sample_mj(rng, theta_up, nu), gamma_up, -1.0)
+        us.append(u)
+        if log:
+            log(f"shock: four-velocities of species {k}")
+    qabs = charge_from_skin_depth(c, Rp, ppc_up, gamma_up)
+    N = nx * ny * nz
+    E = np.zeros((3, N))
+    B = np.zeros((3, N))
+    meta = dict(workload="shock", x_shock=x_shock, ppc_down=ppc_down, ppc_up=ppc_up, theta_down=theta_down,
+                gamma_up=gamma_up, theta_up=theta_up, Rp=Rp, walls=True)
+    return _pair(3, n, c, qabs, x, us[0], x.copy(), us[1], E, B, meta)
 
 
 def thermal_box(nx: int, ny: int, ppc: int, theta: float, Rp: float = 3.0, c: float = 0.45,

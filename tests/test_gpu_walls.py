@@ -32,7 +32,8 @@ def rel(a, b):
 def make_sim(plasma, T, prec, **kw):
     from paper_1906_06306_amd.sim import PicSim
     print(f"[gpu] walled PicSim D={plasma.D} n={plasma.n} T={T} prec={prec} np={plasma.nparticles}", flush=True)
-    return PicSim(plasma, tile=T, precision=prec, walls=True, capacity_factor=2.0, **kw)
+    kw.setdefault("capacity_factor", 2.0)
+    return PicSim(plasma, tile=T, precision=prec, walls=True, **kw)
 
 
 def slots_in_order(sim, species):
@@ -158,4 +159,35 @@ def test_walls_reject_unfused_and_adjoint():
     la, ua, lE, lB = sim.adjoint_buffers()
     assert L.lib().pic_adjoint_step(sim.ctx, la.data_ptr(), ua.data_ptr(), lE.data_ptr(), lB.data_ptr()) \
         == L.PIC_E_ARG
+    sim.close()
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_shock_reduced_matches_oracle(prec, persistent):
+    """The 3D pre-shocked plasma between walls at 1/512 of its volume
+    (128 x 16 x 16 cells, 917,504 particles, 8^3 tiles holding 4:1 uneven
+    counts): one fused step, per-tile and persistent walker, against the
+    oracle's wall step; then 10 more steps keep Gauss's residual off the
+    wall plane."""
+    from paper_1906_06306_amd import _lib as L
+    plasma = synth.shock(n=(128, 16, 16), x_shock=32)
+    opts = L.PIC_OPT_PERSISTENT if persistent else 0
+    sim = make_sim(plasma, (8, 8, 8), prec, options=opts, tile_capacity="auto", capacity_factor=1.5)
+    st = common_state(sim, plasma)
+    sim.step(1, fused=True, half_b_in_push=True)
+    st.step(1, walls=True)
+    assert sim.error() == 0
+    tol = TOL[prec]
+    E, B, J = sim.fields_host(0)
+    assert rel(J, st.J) < tol, rel(J, st.J)
+    assert rel(E, st.E) < tol and rel(B, st.B) < tol, (rel(E, st.E), rel(B, st.B))
+    if prec == "fp64":
+        r0 = common_state(sim, plasma).gauss_residual()
+        sim.step(10, fused=True, half_b_in_push=True)
+        assert sim.error() == 0
+        r = common_state(sim, plasma).gauss_residual()
+        interior = (np.arange(r.size) % 128) != 0
+        assert np.abs(r - r0)[interior].max() < 1e-12
+        assert sim.diagnostics()["particles"] == plasma.nparticles
     sim.close()
