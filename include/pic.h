@@ -192,7 +192,8 @@ typedef struct {
 /* FP64 diagnostics of the current state (Eqs. fdE/fdB, App. B). */
 typedef struct {
     double field_energy;     /* 1/2 sum(E^2 + B^2) over all boxes           */
-    double kinetic_energy;   /* sum m c^2 (gamma - 1) over all particles     */
+    double kinetic_energy;   /* sum m c^2 (gamma - 1) over all particles, c
+                                the Courant number (code units, App. A)    */
     double gauss_max;        /* max |div- E - rho| on nodes                  */
     double divb_max;         /* max |div+ B| on cell centres                 */
     double charge_total;     /* sum rho                                      */
@@ -257,7 +258,9 @@ pic_status pic_step(pic_ctx *ctx, uint32_t flags);
 /* Capture nsteps calls of pic_step(flags) into a HIP graph on the context's
  * stream (after one eager step, which also sets kernel attributes).  The
  * steps contain no memset nodes (fills are kernels).  Replaces a previous
- * graph.  PIC_E_STATE if called between a push and its migration. */
+ * graph.  PIC_E_STATE if called between a push and its migration; PIC_E_ARG
+ * if the context is bound to the default (null) stream, which cannot be
+ * captured. */
 pic_status pic_graph_capture(pic_ctx *ctx, int32_t nsteps, uint32_t flags);
 
 /* Replay the captured steps on the context's stream. */
@@ -270,6 +273,10 @@ pic_status pic_error(pic_ctx *ctx);
 /* FP64 diagnostics of the current state.  Synchronises the stream.  Its
  * return value includes the latched device error bits (then cleared). */
 pic_status pic_diagnostics(pic_ctx *ctx, pic_diag *out);
+
+/* The same diagnostics per box: out is a host array of n_boxes entries
+ * (near_face and error_bits are the context's, repeated in every entry). */
+pic_status pic_diagnostics_boxes(pic_ctx *ctx, pic_diag *out);
 
 /* Reverse mode.  The adjoint of one step maps the sensitivities of a loss
  * to the state after the step (x^{n+1}, u^{n+1/2}, E^{n+1}, B^{n+1/2}) to

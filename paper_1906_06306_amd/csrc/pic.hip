@@ -580,7 +580,7 @@ struct Impl {
         return PIC_OK;
     }
 
-    static pic_status diag(pic_ctx *x, pic_diag *out)
+    static pic_status diag(pic_ctx *x, pic_diag *out, bool per_box)
     {
         Params<R> p = params<R>(x);
         const Layout &L = x->L;
@@ -599,17 +599,19 @@ struct Impl {
         unsigned long long nf = 0;
         HIP_OK(hipMemcpyAsync(&nf, p.nearface, sizeof nf, hipMemcpyDeviceToHost, x->stream));
         HIP_OK(hipStreamSynchronize(x->stream));
-        memset(out, 0, sizeof *out);
+        const int nout = per_box ? x->nb : 1;
+        memset(out, 0, nout * sizeof *out);
         for (int64_t t = 0; t < L.pub.tiles_total; ++t) {
             const double *o = &h[t * pic::NPART];
-            out->field_energy += o[0];
-            out->divb_max = std::max(out->divb_max, o[1]);
-            out->kinetic_energy += o[2];
-            out->particles += (int64_t)o[3];
-            out->gauss_max = std::max(out->gauss_max, o[4]);
-            out->charge_total += o[5];
+            pic_diag *d = per_box ? out + L.tiles[t].box : out;
+            d->field_energy += o[0];
+            d->divb_max = std::max(d->divb_max, o[1]);
+            d->kinetic_energy += o[2];
+            d->particles += (int64_t)o[3];
+            d->gauss_max = std::max(d->gauss_max, o[4]);
+            d->charge_total += o[5];
         }
-        out->near_face = (int64_t)nf;
+        for (int k = 0; k < nout; ++k) out[k].near_face = (int64_t)nf;
         return PIC_OK;
     }
 };
@@ -636,7 +638,7 @@ pic_status do_fdtd(pic_ctx *x, int phase) { PIC_DISPATCH(x, fdtd(x, phase)); }
 pic_status do_push(pic_ctx *x, bool fused, bool halfb) { PIC_DISPATCH(x, push(x, fused, halfb)); }
 pic_status do_deposit(pic_ctx *x, bool unfused) { PIC_DISPATCH(x, deposit(x, unfused)); }
 pic_status do_migrate(pic_ctx *x, bool out, bool in, bool sort) { PIC_DISPATCH(x, migrate(x, out, in, sort)); }
-pic_status do_diag(pic_ctx *x, pic_diag *o) { PIC_DISPATCH(x, diag(x, o)); }
+pic_status do_diag(pic_ctx *x, pic_diag *o, bool per_box) { PIC_DISPATCH(x, diag(x, o, per_box)); }
 pic_status do_adjoint(pic_ctx *x, void *a, void *b, void *c, void *d) { PIC_DISPATCH(x, adjoint(x, a, b, c, d)); }
 pic_status do_unpermute(pic_ctx *x, const void *a, const void *b, void *c, void *d, int64_t s)
 {
@@ -843,6 +845,7 @@ pic_status pic_graph_capture(pic_ctx *x, int32_t nsteps, uint32_t flags)
 {
     if (!x || nsteps < 1) return fail(PIC_E_ARG, "need a context and nsteps >= 1");
     if (x->state != 0) return fail(PIC_E_STATE, "capture must start between steps");
+    if (!x->stream) return fail(PIC_E_ARG, "graph capture needs a context on a created (non-default) stream");
     if (x->graph) {
         HIP_OK(hipGraphExecDestroy(x->graph));
         x->graph = nullptr;
@@ -889,11 +892,22 @@ pic_status pic_error(pic_ctx *x)
 pic_status pic_diagnostics(pic_ctx *x, pic_diag *out)
 {
     if (!x || !out) return fail(PIC_E_ARG, "null argument");
-    pic_status st = do_diag(x, out);
+    pic_status st = do_diag(x, out, false);
     if (st) return st;
     int32_t bits = 0;
     if ((st = read_error(x, &bits))) return st;
     out->error_bits = bits;
+    return error_status(bits);
+}
+
+pic_status pic_diagnostics_boxes(pic_ctx *x, pic_diag *out)
+{
+    if (!x || !out) return fail(PIC_E_ARG, "null argument");
+    pic_status st = do_diag(x, out, true);
+    if (st) return st;
+    int32_t bits = 0;
+    if ((st = read_error(x, &bits))) return st;
+    for (int b = 0; b < x->nb; ++b) out[b].error_bits = bits;
     return error_status(bits);
 }
 

@@ -254,6 +254,16 @@ class PicSim:
                     divb_max=d.divb_max, charge_total=d.charge_total, particles=d.particles,
                     near_face=d.near_face, error_bits=d.error_bits, status=code)
 
+    def box_diagnostics(self) -> list:
+        """Diagnostics of every box (FP64), one dict per box."""
+        arr = (L.PicDiag * self.nb)()
+        code = L.lib().pic_diagnostics_boxes(self.ctx, ctypes.cast(arr, ctypes.c_void_p))
+        if code not in (0,) and code < (1 << 8):
+            L.check(code)
+        return [dict(field_energy=d.field_energy, kinetic_energy=d.kinetic_energy, gauss_max=d.gauss_max,
+                     divb_max=d.divb_max, charge_total=d.charge_total, particles=d.particles,
+                     error_bits=d.error_bits, status=code) for d in arr]
+
     def close(self):
         if getattr(self, "ctx", None):
             L.lib().pic_destroy(self.ctx)
