@@ -149,13 +149,35 @@ def run_gpu(plasma, args, precision, steps, warmup, tile, profile_only=False):
 
 
 def cpu_oracle_rate(plasma, steps):
-    """The FP64 oracle, as it stands, on full steps of the same workload."""
+    """The FP64 oracle, as it stands, on full steps of the same workload;
+    also returns E, B, J after its first step (the reference the GPU paths'
+    one-step error is stated against)."""
     import oracle
     st = oracle.State(plasma)
     t0 = time.perf_counter()
-    st.step(steps)
-    dt = time.perf_counter() - t0
-    return plasma.nparticles * steps / dt, dt
+    st.step(1)
+    t1 = time.perf_counter()
+    first = (st.E.copy(), st.B.copy(), st.J.copy())
+    t2 = time.perf_counter()
+    st.step(steps - 1)
+    dt = (t1 - t0) + (time.perf_counter() - t2)
+    return plasma.nparticles * steps / dt, dt, first
+
+
+def one_step_error(plasma, precision, tile, ref):
+    """Relative L2 of E, B, J after one GPU step from the input state
+    against the oracle's first step (input rounding included)."""
+    import torch
+    from paper_1906_06306_amd.sim import PicSim
+    sim = PicSim(plasma, tile=(tile, tile), precision=precision, capacity_factor=3.0)
+    sim.step(1, fused=True, half_b_in_push=True)
+    out = {}
+    for name, g, r in zip(("E", "B", "J"), sim.fields_host(0), ref):
+        out[name] = float(np.linalg.norm(g - r) / np.linalg.norm(r))
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return out
 
 
 def pick_tile(plasma, args, precision):
@@ -438,12 +460,16 @@ def main():
         log(f"fp64 run, tile {tile64}")
         r64 = run_gpu(plasma, args, "fp64", args.steps, args.warmup, tile64)
     cpu = None
+    err32 = err64 = None
     if not args.no_cpu:
         log(f"cpu oracle: {args.cpu_steps} full steps")
-        rate, sec = cpu_oracle_rate(plasma, args.cpu_steps)
+        rate, sec, first = cpu_oracle_rate(plasma, args.cpu_steps)
         cpu = {"value": rate, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
                "sample": f"{args.cpu_steps} full steps of the same {args.n}^2 workload ({n_p} particles), "
                          f"single-threaded FP64 C oracle, {sec:.1f} s"}
+        log("one-step error of the GPU paths against the oracle")
+        err32 = one_step_error(plasma, "fp32", tile32, first)
+        err64 = one_step_error(plasma, "fp64", tile64 if r64 is not None else tile32, first)
     if r32["diag"]["status"] != 0:
         log(f"WARNING: device status {r32['diag']['status']} after the FP32 run (capacity or "
             "numerical error): the measurement is invalid; raise --capacity")
@@ -477,13 +503,15 @@ def main():
         "diagnostics_fp32": {k: r32["diag"][k] for k in ("gauss_max", "divb_max", "field_energy",
                                                          "kinetic_energy", "particles", "status")},
         "cpu_baseline": cpu,
+        "fp32_vs_oracle_1step_rel_l2": err32,
     }
     if r64 is not None:
         v64 = n_p * args.steps / r64["seconds"]
         out["fp64"] = {"value": v64, "ms_per_step": r64["seconds"] / args.steps * 1e3,
                        "push_ms": r64["push_ms"], "speedup_fp32_over_fp64": value / v64,
                        "tile": tile64, "autotune_ms_per_step": tune64,
-                       "gauss_max": r64["diag"]["gauss_max"], "status": r64["diag"]["status"]}
+                       "gauss_max": r64["diag"]["gauss_max"], "status": r64["diag"]["status"],
+                       "vs_oracle_1step_rel_l2": err64}
     print(json.dumps(out), flush=True)
 
 

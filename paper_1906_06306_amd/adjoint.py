@@ -1,6 +1,7 @@
 """Reverse mode over windows of fused steps, with checkpointed recomputation.
 
-The forward run keeps a copy of the workspace every ``window`` steps.  The
+The forward run keeps a copy of the state regions of the workspace (fields,
+particle planes, segment counts, origin ids) every ``window`` steps.  The
 reverse sweep visits the windows last to first: it restores the window's
 checkpoint, re-runs the window while keeping every intermediate state, and
 then, step by step backwards, maps the particle adjoints across the step's
@@ -26,7 +27,7 @@ STEP_FLAGS = L.PIC_FUSED | L.PIC_PUSH_HALF_B
 
 
 def forward(sim: PicSim, nsteps: int, window: int = 8) -> dict:
-    """Run nsteps tracked fused steps; return {step: workspace copy} at the
+    """Run nsteps tracked fused steps; return {step: state copy} at the
     window starts."""
     if not sim.cfg.options & L.PIC_OPT_TRACK:
         raise ValueError("the simulation needs options=PIC_OPT_TRACK")

@@ -196,12 +196,37 @@ class PicSim:
             L.check(fn(self.ctx))
 
     # ------------------------------------------------------ reverse mode
-    def snapshot(self) -> torch.Tensor:
-        """Copy of the whole workspace (state, tables and origin ids)."""
-        return self.ws.clone()
+    def _state_ranges(self):
+        """Byte ranges of the workspace that hold the state between steps:
+        E, B, positions, four-velocities, segment counts, the error word and
+        (with origin tracking) the origin ids.  Everything else is constant
+        tables or scratch that the next step rewrites."""
+        lay = self.layout
+        w = int(lay.elem_bytes)
+        N = int(lay.cells_total)
+        cap = int(lay.capacity_total)
+        nts = int(lay.tiles_total) * self.ns
+        r = [(lay.off_E, 3 * N * w), (lay.off_B, 3 * N * w), (lay.off_pos, self.D * cap * w),
+             (lay.off_u, 3 * cap * w), (lay.off_seg_count, nts * 4), (lay.off_error, 4)]
+        if self.cfg.options & L.PIC_OPT_TRACK:
+            r.append((lay.off_ids, cap * 4))
+        r.sort()
+        merged = []
+        for off, n in r:
+            off = int(off)
+            if merged and off - (merged[-1][0] + merged[-1][1]) <= 256:
+                merged[-1][1] = off + n - merged[-1][0]
+            else:
+                merged.append([off, n])
+        return [(self._shift + off, n) for off, n in merged]
 
-    def restore(self, snap: torch.Tensor):
-        self.ws.copy_(snap)
+    def snapshot(self) -> list:
+        """Copy of the state regions of the workspace (see _state_ranges)."""
+        return [self.ws[a:a + n].clone() for a, n in self._state_ranges()]
+
+    def restore(self, snap: list):
+        for (a, n), t in zip(self._state_ranges(), snap):
+            self.ws[a:a + n].copy_(t)
 
     def adjoint_buffers(self):
         """Zeroed particle and field adjoint arrays in the state layout."""
