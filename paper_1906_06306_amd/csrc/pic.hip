@@ -56,7 +56,7 @@ struct Layout {
     uint64_t off_tmp, off_jblk, off_rblk, off_part, off_ob_pos, off_ob_u, off_ob_dir, off_ob_cnt;
     uint64_t off_tiles, off_charge, off_qm, off_mass, off_order, off_queue;
     uint64_t off_key, off_xl, off_hist;
-    uint64_t off_ob_ids, off_adj_lj, off_adj_eblk, off_adj_bblk;
+    uint64_t off_ob_ids, off_adj_lj, off_adj_eblk, off_adj_bblk, off_ob_boff, off_ob_idx;
     int64_t fblk_cells, n_input;
     int64_t jblk_cells, rblk_cells, max_count, max_ntb, nchunks_max, ob_dir_stride;
     std::vector<TileDesc> tiles;
@@ -221,6 +221,8 @@ pic_status make_layout(const pic_config *c, const int64_t *counts, Layout &L)
     L.ob_dir_stride = obcap + group;   // padding slots take the codes of stayers
     L.off_ob_dir = take(tiles * ns * L.ob_dir_stride * 4);
     L.off_ob_cnt = take(tiles * ns * 4);
+    L.off_ob_boff = take(tiles * ns * (pic::ncodes<3>() + 1) * 4);
+    L.off_ob_idx = take(tiles * ns * obcap * 4);
     L.off_tiles = take(tiles * sizeof(TileDesc));
     L.off_charge = take(nb * ns * w);
     L.off_qm = take(nb * ns * w);
@@ -295,6 +297,8 @@ Params<R> params(pic_ctx *x)
     p.ob_u = reinterpret_cast<R *>(ws + L.off_ob_u);
     p.ob_dir = reinterpret_cast<int32_t *>(ws + L.off_ob_dir);
     p.ob_cnt = reinterpret_cast<int32_t *>(ws + L.off_ob_cnt);
+    p.ob_boff = reinterpret_cast<int32_t *>(ws + L.off_ob_boff);
+    p.ob_idx = reinterpret_cast<int32_t *>(ws + L.off_ob_idx);
     p.ob_cap = L.pub.outbox_capacity;
     p.ob_dir_stride = L.ob_dir_stride;
     p.tmp = reinterpret_cast<R *>(ws + L.off_tmp);
@@ -445,6 +449,7 @@ struct Impl {
             HIP_OK(hipGetLastError());
         }
         if (need_in) {
+            hipLaunchKernelGGL((pic::k_migrate_bucket<R, D>), g, dim3(256), 0, x->stream, p);
             hipLaunchKernelGGL((pic::k_migrate_in<R, D>), g, dim3(x->block), 0, x->stream, p);
             HIP_OK(hipGetLastError());
         }

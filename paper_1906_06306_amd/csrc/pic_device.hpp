@@ -58,6 +58,8 @@ struct Params {
     const int32_t *order;     // tile visiting order of the persistent walker
     int32_t *ids;             // [cap_total] origin of each particle, or null
     int32_t *ob_ids;          // [tile*species][ob_cap] origin of each leaver
+    int32_t *ob_boff;         // [tile*species][ncodes+1] outbox bucket starts by direction code
+    int32_t *ob_idx;          // [tile*species][ob_cap] outbox slots in bucket order
 };
 
 enum : int32_t { ERR_CAPACITY = 1, ERR_CFL = 2, ERR_NONFINITE = 4, ERR_OUT_OF_TILE = 8, ERR_ADJ_MAP = 16 };

@@ -576,26 +576,88 @@ __global__ void __launch_bounds__(1024) k_migrate_out(Params<R> p)
     }
 }
 
+// Bucket every tile's outbox by direction code (stable counting sort): for
+// each (tile, species) the bucket starts ob_boff[ncodes + 1] and the outbox
+// slots in bucket order ob_idx[ob_cap], so that each neighbour reads exactly
+// the leavers addressed to it.  The rank of an entry among equal codes of
+// its wave comes from ballots on the code bits; waves are ordered through
+// per-wave counts in LDS.
+template <typename R, int D>
+__global__ void __launch_bounds__(1024) k_migrate_bucket(Params<R> p)
+{
+    constexpr int NC = ncodes<D>();
+    __shared__ int sCnt[MAX_WAVES * NC];
+    __shared__ int sBase[NC + 1];
+    const int t = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int s = 0; s < p.nspecies; ++s) {
+        const int ts = t * p.nspecies + s;
+        const int n = (int)min((int64_t)p.ob_cnt[ts], p.ob_cap);
+        const int32_t *dir = p.ob_dir + (int64_t)ts * p.ob_dir_stride;
+        int32_t *boff = p.ob_boff + (int64_t)ts * (NC + 1);
+        int32_t *idx = p.ob_idx + (int64_t)ts * p.ob_cap;
+        // histogram and bucket starts
+        for (int k = threadIdx.x; k <= NC; k += blockDim.x) sBase[k] = 0;
+        __syncthreads();
+        for (int k = threadIdx.x; k < n; k += blockDim.x) atomicAdd(&sBase[dir[k] + 1], 1);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int c = 0; c < NC; ++c) sBase[c + 1] += sBase[c];
+            for (int c = 0; c <= NC; ++c) boff[c] = sBase[c];
+        }
+        __syncthreads();
+        // stable scatter, one work-group-wide chunk at a time
+        for (int c0 = 0; c0 < n; c0 += blockDim.x) {
+            for (int k = threadIdx.x; k < nw * NC; k += blockDim.x) sCnt[k] = 0;
+            __syncthreads();
+            const int k = c0 + (int)threadIdx.x;
+            const bool valid = k < n;
+            const int code = valid ? dir[k] : 0;
+            unsigned long long m = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 5; ++b) {
+                const unsigned long long bb = __ballot((code >> b) & 1);
+                m &= ((code >> b) & 1) ? bb : ~bb;
+            }
+            const int rank = lanes_below(m);
+            if (valid && rank == 0) sCnt[wave * NC + code] = __popcll(m);
+            __syncthreads();
+            if (valid) {
+                int off = sBase[code] + rank;
+                for (int w = 0; w < wave; ++w) off += sCnt[w * NC + code];
+                idx[off] = k;
+            }
+            __syncthreads();
+            if ((int)threadIdx.x < NC) {
+                int add = 0;
+                for (int w = 0; w < nw; ++w) add += sCnt[w * NC + threadIdx.x];
+                sBase[threadIdx.x] += add;
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // Receive incoming particles: append, per direction code in increasing
-// order, the neighbour outbox entries addressed to this tile.  The entries
-// of all neighbours are walked as one index space (direction-major), so a
-// tile needs a few chunks instead of one dependent round per neighbour.
+// order, the leavers of the neighbour that moved towards this tile (its
+// bucket for that code, in the neighbour's order).  The buckets of all
+// neighbours are walked as one index space (direction-major).
 template <typename R, int D>
 __global__ void __launch_bounds__(1024) k_migrate_in(Params<R> p)
 {
-    __shared__ int sTot[2 * MAX_WAVES];
-    __shared__ int sOff[ncodes<D>() + 1];
-    __shared__ int sSrc[ncodes<D>()];
+    constexpr int NC = ncodes<D>();
+    __shared__ int sOff[NC + 1];
+    __shared__ int sSrc[NC];
+    __shared__ int sB0[NC];
     const int t = blockIdx.x;
     const TileDesc td = p.tiles[t];
     const int64_t cap = p.cap_total;
-    int parity = 0;
     for (int s = 0; s < p.nspecies; ++s) {
         const int ts = t * p.nspecies + s;
         const int64_t so = p.seg_off[ts];
         const int scap = p.seg_cap[ts];
-        int cnt = p.seg_cnt[ts];
-        if ((int)threadIdx.x < ncodes<D>()) {
+        const int cnt = p.seg_cnt[ts];
+        if ((int)threadIdx.x < NC) {
             const int code = threadIdx.x;
             int nc[3] = {0, 0, 0}, rem = code;
 #pragma unroll
@@ -607,45 +669,37 @@ __global__ void __launch_bounds__(1024) k_migrate_in(Params<R> p)
                 }
             }
             const int sts = (td.tile0 + nc[0] + td.nt[0] * (nc[1] + td.nt[1] * nc[2])) * p.nspecies + s;
+            const int32_t *boff = p.ob_boff + (int64_t)sts * (NC + 1);
             sSrc[code] = sts;
-            sOff[code + 1] = code == centre_code<D>() ? 0 : (int)min((int64_t)p.ob_cnt[sts], p.ob_cap);
+            sB0[code] = boff[code];
+            sOff[code + 1] = code == centre_code<D>() ? 0 : boff[code + 1] - boff[code];
         }
         __syncthreads();
         if (threadIdx.x == 0) {
             sOff[0] = 0;
-            for (int k = 0; k < ncodes<D>(); ++k) sOff[k + 1] += sOff[k];
+            for (int k = 0; k < NC; ++k) sOff[k + 1] += sOff[k];
         }
         __syncthreads();
-        const int total = sOff[ncodes<D>()];
-        for (int c0 = 0; c0 < total; c0 += blockDim.x) {
-            const int e = c0 + threadIdx.x;
-            bool take = false;
+        const int total = sOff[NC];
+        int32_t errs = 0;
+        for (int e = threadIdx.x; e < total; e += blockDim.x) {
             int code = 0;
-            int64_t src = 0;
-            if (e < total) {
-                while (sOff[code + 1] <= e) ++code;
-                src = (int64_t)sSrc[code] * p.ob_cap + (e - sOff[code]);
-                take = p.ob_dir[(int64_t)sSrc[code] * p.ob_dir_stride + (e - sOff[code])] == code;
-            }
-            int tot;
-            const int pre = wg_scan_flag(take, sTot, parity, tot);
-            parity ^= 1;
-            if (take) {
-                const int dst = cnt + pre;
-                if (dst < scap) {
-                    const int64_t sts = src / p.ob_cap, k = src - sts * p.ob_cap;
-                    if (p.ids) p.ids[so + dst] = p.ob_ids[sts * p.ob_cap + k];
+            while (sOff[code + 1] <= e) ++code;
+            const int64_t sts = sSrc[code];
+            const int64_t k = p.ob_idx[sts * p.ob_cap + sB0[code] + (e - sOff[code])];
+            const int dst = cnt + e;
+            if (dst < scap) {
+                if (p.ids) p.ids[so + dst] = p.ob_ids[sts * p.ob_cap + k];
 #pragma unroll
-                    for (int d = 0; d < D; ++d) p.pos[d * cap + so + dst] = p.ob_pos[sts * p.ob_cap * D + d * p.ob_cap + k];
+                for (int d = 0; d < D; ++d) p.pos[d * cap + so + dst] = p.ob_pos[sts * p.ob_cap * D + d * p.ob_cap + k];
 #pragma unroll
-                    for (int mm = 0; mm < 3; ++mm) p.u[mm * cap + so + dst] = p.ob_u[sts * p.ob_cap * 3 + mm * p.ob_cap + k];
-                } else {
-                    latch(p.err, ERR_CAPACITY);
-                }
+                for (int mm = 0; mm < 3; ++mm) p.u[mm * cap + so + dst] = p.ob_u[sts * p.ob_cap * 3 + mm * p.ob_cap + k];
+            } else {
+                errs |= ERR_CAPACITY;
             }
-            cnt += tot;
         }
-        if (threadIdx.x == 0) p.seg_cnt[ts] = min(cnt, scap);
+        if (errs) latch(p.err, errs);
+        if (threadIdx.x == 0) p.seg_cnt[ts] = min(cnt + total, scap);
         __syncthreads();   // sOff / sSrc are rewritten for the next species
     }
 }
