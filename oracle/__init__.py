@@ -56,6 +56,10 @@ def lib():
             "orc_wrap": (None, [I, P, I64, P]),
             "orc_step": (I, [I, P, Dbl, I, P, P, P, P, P, P, P, P]),
             "orc_step_walls": (I, [I, P, Dbl, I, P, P, P, P, P, P, P, P]),
+            "orc_step_opts": (I, [I, P, Dbl, I, P, P, P, P, P, P, P, P, I, I, I]),
+            "orc_vay": (None, [I64, Dbl, Dbl, P, P, P]),
+            "orc_hc": (None, [I64, Dbl, Dbl, P, P, P]),
+            "orc_filter_binomial": (I, [I, P, I, I, P]),
             "orc_rho": (None, [I, P, Dbl, I64, P, P]),
             "orc_div_edge": (None, [P, P, P]),
             "orc_div_face": (None, [P, P, P]),
@@ -120,6 +124,25 @@ def interp(D, n, E, B, x, walls: bool = False):
 def boris(c, s, Ep, Bp, u):
     """u (3, np) updated in place."""
     lib().orc_boris(u.shape[1], float(c), float(s), _p(_f64(Ep)), _p(_f64(Bp)), _p(u))
+
+
+def vay(c, s, Ep, Bp, u):
+    """Vay pusher; u (3, np) updated in place."""
+    lib().orc_vay(u.shape[1], float(c), float(s), _p(_f64(Ep)), _p(_f64(Bp)), _p(u))
+
+
+def higuera_cary(c, s, Ep, Bp, u):
+    """Higuera-Cary pusher; u (3, np) updated in place."""
+    lib().orc_hc(u.shape[1], float(c), float(s), _p(_f64(Ep)), _p(_f64(Bp)), _p(u))
+
+
+def filter_binomial(D, n, passes, F):
+    """passes of the 3-point binomial filter on F (planes, N) in place."""
+    dims = _dims(n)
+    F2 = F.reshape(-1, int(np.prod(dims)))
+    assert F2.flags.c_contiguous and F2.dtype == np.float64
+    if lib().orc_filter_binomial(D, _p(dims), int(passes), F2.shape[0], _p(F2)) != 0:
+        raise MemoryError("oracle filter could not allocate scratch")
 
 
 def move(D, c, u, x):
@@ -190,10 +213,15 @@ class State:
         self.s = [float(s.s) for s in plasma.species]
         self.m = [float(s.m) for s in plasma.species]
 
-    def step(self, nsteps: int = 1, walls: bool = False):
+    def step(self, nsteps: int = 1, walls: bool = False, pusher: int = 0, filter_passes: int = 0):
         """nsteps full steps; walls=True: conducting, reflecting walls at
-        x = 0 and x = n0 (y, z periodic), else periodic everywhere."""
-        fn = lib().orc_step_walls if walls else lib().orc_step
+        x = 0 and x = n0 (y, z periodic), else periodic everywhere; pusher
+        0 Boris, 1 Vay, 2 Higuera-Cary; filter_passes binomial passes on J."""
+        if pusher or filter_passes:
+            extra = (int(walls), int(pusher), int(filter_passes))
+            fn = lambda *a: lib().orc_step_opts(*a, *extra)
+        else:
+            fn = lib().orc_step_walls if walls else lib().orc_step
         ns = len(self.x)
         dims = _dims(self.n)
         n_per = np.array([x.shape[1] for x in self.x], dtype=np.int64)

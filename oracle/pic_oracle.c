@@ -604,6 +604,221 @@ int orc_step_walls(int D, const int n[3], double c, int nspecies, const int64_t 
 }
 
 /* ====================================================================== */
+/* Solvers the paper lists beside the Boris pusher and the plain current
+ * (its table of modules and solvers): the Vay and Higuera-Cary pushers and
+ * the 3-point binomial current filter, written from their published
+ * definitions in the units of App. C (velocities w = c u inside an update,
+ * half electric kick eps = s E / 2, rotation vector tau = s B / (2 c), so
+ * that Boris uses t = tau / gamma_1).                                     */
+
+static double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+static void cross3(const double a[3], const double b[3], double o[3])
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* Lorentz factor of the implicit rotation: the gamma that solves
+ * w1 = w' + (w1 / gamma) x tau, from gamma'^2 = 1 + |w'|^2/c^2 and
+ * u* = w'.tau / c (Vay 2008; Higuera and Cary 2017). */
+static double implicit_gamma(const double wp[3], const double tau[3], double c)
+{
+    double g2 = 1.0 + dot3(wp, wp) / (c * c);
+    double us = dot3(wp, tau) / c;
+    double t2 = dot3(tau, tau);
+    double sig = g2 - t2;
+    return sqrt(0.5 * (sig + sqrt(sig * sig + 4.0 * (t2 + us * us))));
+}
+
+/* w <- s (w + (w.t) t + w x t), s = 1/(1+|t|^2) */
+static void exact_rotation(const double w[3], const double t[3], double o[3])
+{
+    double wt = dot3(w, t), sf = 1.0 / (1.0 + dot3(t, t)), x[3];
+    cross3(w, t, x);
+    for (int i = 0; i < 3; ++i) o[i] = sf * (w[i] + wt * t[i] + x[i]);
+}
+
+/* Vay pusher: the full electric kick and half the magnetic kick with the old
+ * velocity, then the other magnetic half with the new velocity, solved
+ * exactly for its Lorentz factor. */
+void orc_vay(int64_t np, double c, double s, const double *Ep, const double *Bp, double *u)
+{
+    for (int64_t p = 0; p < np; ++p) {
+        double w0[3], tau[3], wp[3], vt[3], t[3], w1[3];
+        for (int i = 0; i < 3; ++i) {
+            w0[i] = c * u[i * np + p];
+            tau[i] = s * Bp[i * np + p] / (2.0 * c);
+        }
+        double g0 = sqrt(1.0 + dot3(w0, w0) / (c * c));
+        double v0[3] = {w0[0] / g0, w0[1] / g0, w0[2] / g0};
+        cross3(v0, tau, vt);
+        for (int i = 0; i < 3; ++i) wp[i] = w0[i] + s * Ep[i * np + p] + vt[i];
+        double g1 = implicit_gamma(wp, tau, c);
+        for (int i = 0; i < 3; ++i) t[i] = tau[i] / g1;
+        exact_rotation(wp, t, w1);
+        for (int i = 0; i < 3; ++i) u[i * np + p] = w1[i] / c;
+    }
+}
+
+/* Higuera-Cary pusher: Boris's split (half kick, rotation, half kick) with
+ * the rotation's Lorentz factor taken from the implicit (volume-preserving)
+ * relation instead of gamma_1. */
+void orc_hc(int64_t np, double c, double s, const double *Ep, const double *Bp, double *u)
+{
+    for (int64_t p = 0; p < np; ++p) {
+        double eps[3], tau[3], wm[3], t[3], wpl[3], x[3];
+        for (int i = 0; i < 3; ++i) {
+            eps[i] = 0.5 * s * Ep[i * np + p];
+            tau[i] = s * Bp[i * np + p] / (2.0 * c);
+            wm[i] = c * u[i * np + p] + eps[i];
+        }
+        double g = implicit_gamma(wm, tau, c);
+        for (int i = 0; i < 3; ++i) t[i] = tau[i] / g;
+        exact_rotation(wm, t, wpl);
+        cross3(wpl, t, x);
+        for (int i = 0; i < 3; ++i) u[i * np + p] = (wpl[i] + eps[i] + x[i]) / c;
+    }
+}
+
+/* Binomial current filter: each pass replaces every value by
+ * (F[i-1] + 2 F[i] + F[i+1]) / 4 along every grid dimension in turn
+ * (periodic), on nplanes planes of the field. */
+int orc_filter_binomial(int D, const int n[3], int passes, int nplanes, double *F)
+{
+    int64_t N = ncells(n);
+    double *tmp = malloc(sizeof(double) * (size_t)N);
+    if (!tmp) return -1;
+    for (int pass = 0; pass < passes; ++pass)
+        for (int m = 0; m < nplanes; ++m) {
+            double *P = F + m * N;
+            for (int d = 0; d < D; ++d) {
+                for (int k = 0; k < n[2]; ++k)
+                    for (int j = 0; j < n[1]; ++j)
+                        for (int i = 0; i < n[0]; ++i) {
+                            int64_t lo = d == 0 ? cell(n, i - 1, j, k) : d == 1 ? cell(n, i, j - 1, k) : cell(n, i, j, k - 1);
+                            int64_t hi = d == 0 ? cell(n, i + 1, j, k) : d == 1 ? cell(n, i, j + 1, k) : cell(n, i, j, k + 1);
+                            int64_t c0 = cell(n, i, j, k);
+                            tmp[c0] = 0.25 * P[lo] + 0.5 * P[c0] + 0.25 * P[hi];
+                        }
+                memcpy(P, tmp, sizeof(double) * (size_t)N);
+            }
+        }
+    free(tmp);
+    return 0;
+}
+
+/* One full step with the options the solver table allows: walls in x
+ * (walls = 1, see orc_step_walls), the pusher (0 Boris, 1 Vay,
+ * 2 Higuera-Cary) and the number of binomial filter passes applied to the
+ * current after comp_curr and before add_cur.  With walls = 0, pusher = 0
+ * and passes = 0 it is orc_step; with walls = 1, orc_step_walls.          */
+int orc_step_opts(int D, const int n[3], double c, int nspecies, const int64_t *n_per,
+                  double **x, double **u, const double *q, const double *sgn,
+                  double *E, double *B, double *J, int walls, int pusher, int passes)
+{
+    if (nspecies < 1) return -1;
+    int64_t N = ncells(n);
+    double L = (double)n[0];
+    int64_t npmax = 1;
+    for (int s = 0; s < nspecies; ++s) npmax = n_per[s] > npmax ? n_per[s] : npmax;
+    double *fp = malloc(sizeof(double) * 6 * (size_t)npmax);
+    if (!fp) return -1;
+    double **xold = calloc((size_t)nspecies, sizeof(double *));
+    double **disp = calloc((size_t)nspecies, sizeof(double *));
+    int ok = xold && disp;
+    for (int s = 0; ok && s < nspecies; ++s) {
+        xold[s] = malloc(sizeof(double) * (size_t)(D * n_per[s] + 1));
+        disp[s] = malloc(sizeof(double) * (size_t)(3 * n_per[s] + 1));
+        ok = xold[s] && disp[s];
+    }
+    if (ok) {
+        orc_advance_b(D, n, 0.5 * c, E, B);                       /* push_half_b1 */
+        for (int s = 0; s < nspecies; ++s) {                       /* interp_em, push */
+            int64_t np = n_per[s];
+            memcpy(xold[s], x[s], sizeof(double) * (size_t)(D * np));
+            if (walls) orc_interp_walls(D, n, E, B, np, x[s], fp, fp + 3 * np);
+            else orc_interp(D, n, E, B, np, x[s], fp, fp + 3 * np);
+            if (pusher == 1) orc_vay(np, c, sgn[s], fp, fp + 3 * np, u[s]);
+            else if (pusher == 2) orc_hc(np, c, sgn[s], fp, fp + 3 * np, u[s]);
+            else orc_boris(np, c, sgn[s], fp, fp + 3 * np, u[s]);
+            orc_move(D, np, c, u[s], x[s], disp[s]);
+        }
+        orc_advance_b(D, n, 0.5 * c, E, B);                       /* push_half_b2 */
+        orc_advance_e(D, n, c, B, E);                             /* push_e */
+        memset(J, 0, sizeof(double) * 3 * (size_t)N);             /* comp_curr */
+        for (int s = 0; s < nspecies; ++s) {
+            int64_t np = n_per[s];
+            if (!walls) {
+                orc_zigzag(D, n, q[s], np, xold[s], x[s], disp[s], J);
+                continue;
+            }
+            for (int64_t p = 0; p < np; ++p) {
+                double a[3] = {0, 0, 0}, b[3] = {0, 0, 0}, dn[3] = {0, 0, 0};
+                for (int d = 0; d < D; ++d) {
+                    a[d] = xold[s][d * np + p];
+                    b[d] = x[s][d * np + p];
+                }
+                for (int m = D; m < 3; ++m) dn[m] = disp[s][m * np + p];
+                double bx = b[0];
+                if (bx >= 0.0 && bx < L) {
+                    zigzag_path(D, n, q[s], a, b, dn, J);
+                    continue;
+                }
+                double wx = bx < 0.0 ? 0.0 : L;
+                double t = (wx - a[0]) / (bx - a[0]);
+                double w[3] = {wx, 0, 0}, r[3] = {0, 0, 0}, dn1[3] = {0, 0, 0}, dn2[3] = {0, 0, 0};
+                for (int d = 1; d < D; ++d) w[d] = a[d] + t * (b[d] - a[d]);
+                for (int m = D; m < 3; ++m) {
+                    dn1[m] = t * dn[m];
+                    dn2[m] = dn[m] - dn1[m];
+                }
+                r[0] = bx < 0.0 ? -bx : 2.0 * L - bx;
+                if (r[0] >= L) r[0] = below(L);
+                for (int d = 1; d < D; ++d) r[d] = b[d];
+                zigzag_path(D, n, q[s], a, w, dn1, J);
+                zigzag_path(D, n, q[s], w, r, dn2, J);
+                x[s][p] = r[0];
+                u[s][p] = -u[s][p];
+            }
+        }
+        /* particle communication: periodic wrap (y and z only with walls) */
+        for (int s = 0; s < nspecies; ++s)
+            for (int d = walls ? 1 : 0; d < D; ++d) {
+                double Ld = (double)n[d];
+                for (int64_t p = 0; p < n_per[s]; ++p) {
+                    double v = x[s][d * n_per[s] + p];
+                    if (v < 0.0) v += Ld;
+                    else if (v >= Ld) v -= Ld;
+                    if (v >= Ld) v = 0.0;
+                    x[s][d * n_per[s] + p] = v;
+                }
+            }
+        if (passes > 0 && orc_filter_binomial(D, n, passes, 3, J) != 0) ok = 0;
+        if (ok) {
+            orc_add_current(n, J, E);                             /* add_cur */
+            if (walls)
+                for (int k = 0; k < n[2]; ++k)
+                    for (int j = 0; j < n[1]; ++j) {
+                        int64_t cw = cell(n, 0, j, k);
+                        E[N + cw] = 0.0;
+                        E[2 * N + cw] = 0.0;
+                        B[cw] = 0.0;
+                    }
+        }
+    }
+    for (int s = 0; xold && disp && s < nspecies; ++s) {
+        free(xold[s]);
+        free(disp[s]);
+    }
+    free(xold);
+    free(disp);
+    free(fp);
+    return ok ? 0 : -1;
+}
+
+/* ====================================================================== */
 /* Adjoint (reverse mode) of one full step, written by hand from the
  * forward routines above.  Differentiation of the step is not in the paper;
  * these routines are the exact vector-Jacobian products of orc_step (the
