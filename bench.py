@@ -82,6 +82,10 @@ def parse():
                          "1024x128x128, 4:1 uneven tiles, per-tile and persistent push; ensemble: 64 "
                          "independent 2D3V boxes stepped together (autotuned tile, persistent walker, graph)")
     ap.add_argument("--fd", action="store_true", help="shear-adjoint: also central differences of the FP64 forward")
+    ap.add_argument("--pusher", default="boris", choices=["boris", "vay", "hc"],
+                    help="turbulence: particle pusher of the timed runs")
+    ap.add_argument("--filter-passes", type=int, default=0,
+                    help="turbulence: binomial current filter passes per step")
     return ap.parse_args()
 
 
@@ -104,7 +108,7 @@ def run_gpu(plasma, args, precision, steps, warmup, tile, profile_only=False):
     from paper_1906_06306_amd.sim import PicSim
 
     sim = PicSim(plasma, tile=(tile, tile), precision=precision, block=args.block,
-                 capacity_factor=args.capacity)
+                 capacity_factor=args.capacity, pusher=args.pusher, filter_passes=args.filter_passes)
     stream = torch.cuda.current_stream()
     lib = L.lib()
     ctx = sim.ctx
@@ -121,6 +125,8 @@ def run_gpu(plasma, args, precision, steps, warmup, tile, profile_only=False):
             ev[1].record(stream)
         L.check(lib.pic_fdtd_step(ctx, L.PIC_TWO_HALF_B))
         L.check(lib.pic_deposit_current(ctx, flags))
+        if args.filter_passes:
+            L.check(lib.pic_filter_current(ctx, args.filter_passes))
         L.check(lib.pic_fdtd_step(ctx, L.PIC_CURL_E_ADD_J))
         L.check(lib.pic_sort_migrate(ctx, 0))
 
@@ -493,6 +499,7 @@ def main():
                                f"{args.ppc} ppc/species pair plasma, "
                                "theta=0.3, sigma=10, dB/B0=1 (64 modes), c/w_p=3 cells, Courant 0.45",
                    "particles": n_p, "cells": n_c, "tile": tile32, "block": args.block,
+                   "pusher": args.pusher, "filter_passes": args.filter_passes,
                    "autotune_ms_per_step": tune32},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

@@ -120,7 +120,20 @@ typedef struct {
     uint32_t options;           /* PIC_OPT_* bits, 0 = defaults              */
     const int32_t *box_walls;   /* host [n_boxes] PIC_WALL_* bits, or NULL
                                    (every box periodic in every dimension)   */
+    int32_t pusher;             /* PIC_PUSHER_BORIS (0), _VAY or _HC          */
+    int32_t filter_passes;      /* binomial filter passes pic_step applies to
+                                   J before add_cur (0 = none)               */
 } pic_config;
+
+/* pic_config.pusher (the solver table's pushers): the relativistic Boris
+ * update of App. C; the Vay pusher (full electric kick and half the magnetic
+ * kick with the old velocity, the other half with the new velocity solved
+ * exactly for its Lorentz factor); the Higuera-Cary pusher (Boris's split
+ * with the rotation's Lorentz factor from the same implicit relation).  The
+ * two last keep force-free motion (E + v x B = 0) exact.  Units as App. C. */
+#define PIC_PUSHER_BORIS 0
+#define PIC_PUSHER_VAY 1
+#define PIC_PUSHER_HC 2
 
 /* pic_config.box_walls: conducting, reflecting walls on the node planes
  * x = 0 and x = n0 of the box (y, z stay periodic).  Tangential E (Ey, Ez)
@@ -262,6 +275,12 @@ pic_status pic_step(pic_ctx *ctx, uint32_t flags);
  * if the context is bound to the default (null) stream, which cannot be
  * captured. */
 pic_status pic_graph_capture(pic_ctx *ctx, int32_t nsteps, uint32_t flags);
+
+/* The solver table's 3-point binomial current filter: passes times, J <-
+ * the (1/4, 1/2, 1/4) average along every grid dimension (the 3^D product
+ * stencil), periodic.  pic_step calls it between the current fold and
+ * add_cur with pic_config.filter_passes.  Boxes with walls are rejected. */
+pic_status pic_filter_current(pic_ctx *ctx, int32_t passes);
 
 /* Replay the captured steps on the context's stream. */
 pic_status pic_graph_launch(pic_ctx *ctx);

@@ -56,7 +56,7 @@ struct Layout {
     uint64_t off_tmp, off_jblk, off_rblk, off_part, off_ob_pos, off_ob_u, off_ob_dir, off_ob_cnt;
     uint64_t off_tiles, off_charge, off_qm, off_mass, off_order, off_queue;
     uint64_t off_key, off_xl, off_hist;
-    uint64_t off_ob_ids, off_adj_lj, off_adj_eblk, off_adj_bblk, off_ob_boff, off_ob_idx;
+    uint64_t off_ob_ids, off_adj_lj, off_adj_eblk, off_adj_bblk, off_ob_boff, off_ob_idx, off_jtmp;
     int64_t fblk_cells, n_input;
     int64_t jblk_cells, rblk_cells, max_count, max_ntb, nchunks_max, ob_dir_stride;
     std::vector<TileDesc> tiles;
@@ -77,6 +77,10 @@ pic_status check_config(const pic_config *c)
     if (c->n_boxes < 1) return fail(PIC_E_ARG, "n_boxes must be >= 1");
     if (!c->box_cells || !c->charge || !c->qm || !c->mass) return fail(PIC_E_ARG, "box_cells, charge, qm and mass are required");
     if (!(c->cfl > 0.0) || c->cfl * std::sqrt((double)c->dim) > 1.0) return fail(PIC_E_ARG, "cfl must satisfy 0 < c <= 1/sqrt(D)");
+    if (c->pusher < PIC_PUSHER_BORIS || c->pusher > PIC_PUSHER_HC) return fail(PIC_E_ARG, "unknown pusher %d", c->pusher);
+    if (c->filter_passes < 0) return fail(PIC_E_ARG, "filter_passes must be >= 0");
+    for (int b = 0; c->filter_passes > 0 && c->box_walls && b < c->n_boxes; ++b)
+        if (c->box_walls[b] & PIC_WALL_X) return fail(PIC_E_ARG, "the current filter covers periodic boxes only");
     int blk = c->block ? c->block : 256;
     if (blk < 64 || blk > 1024 || blk % 64) return fail(PIC_E_ARG, "block must be a multiple of 64 in 64..1024");
     for (int d = 0; d < 3; ++d) {
@@ -223,6 +227,7 @@ pic_status make_layout(const pic_config *c, const int64_t *counts, Layout &L)
     L.off_ob_cnt = take(tiles * ns * 4);
     L.off_ob_boff = take(tiles * ns * (pic::ncodes<3>() + 1) * 4);
     L.off_ob_idx = take(tiles * ns * obcap * 4);
+    L.off_jtmp = take(3 * cells * w);
     L.off_tiles = take(tiles * sizeof(TileDesc));
     L.off_charge = take(nb * ns * w);
     L.off_qm = take(nb * ns * w);
@@ -253,6 +258,8 @@ struct pic_ctx {
     bool persistent;    // push as a persistent tile walker
     bool track;         // origin tracking and adjoint scratch present
     bool walls;         // some box has conducting walls in x
+    int pusher;         // PIC_PUSHER_*
+    int filter_passes;  // binomial passes pic_step applies to J
     int n_cu;           // compute units of the device
     hipGraphExec_t graph;   // captured steps, or null
     int graph_steps;
@@ -363,14 +370,14 @@ struct Impl {
         return PIC_OK;
     }
 
-    template <bool FUSED, bool HALFB, typename A, int TC, bool WALLS>
+    template <bool FUSED, bool HALFB, typename A, int TC, bool WALLS, int PUSHER>
     static pic_status push_launch(pic_ctx *x)
     {
         Params<R> p = params<R>(x);
         size_t lds = push_lds(x, FUSED, sizeof(A));
         dim3 b(x->block);
         if (x->persistent) {
-            auto kern = pic::k_push_persistent<R, D, FUSED, HALFB, A, PUSH_UNROLL, TC, WALLS>;
+            auto kern = pic::k_push_persistent<R, D, FUSED, HALFB, A, PUSH_UNROLL, TC, WALLS, PUSHER>;
             pic_status st = set_lds(kern, lds);
             if (st) return st;
             int per_cu = 0;
@@ -381,7 +388,7 @@ struct Impl {
             if (st) return st;
             hipLaunchKernelGGL(kern, dim3((unsigned)grid), b, lds, x->stream, p);
         } else {
-            auto kern = pic::k_push<R, D, FUSED, HALFB, A, PUSH_UNROLL, TC, WALLS>;
+            auto kern = pic::k_push<R, D, FUSED, HALFB, A, PUSH_UNROLL, TC, WALLS, PUSHER>;
             pic_status st = set_lds(kern, lds);
             if (st) return st;
             hipLaunchKernelGGL(kern, dim3((unsigned)x->L.pub.tiles_total), b, lds, x->stream, p);
@@ -396,18 +403,24 @@ struct Impl {
     template <bool FUSED, bool HALFB, typename A>
     static pic_status push_with(pic_ctx *x)
     {
+        if (x->pusher == PIC_PUSHER_VAY)
+            return x->walls ? push_launch<FUSED, HALFB, A, 0, FUSED, pic::PUSHER_VAY>(x)
+                            : push_launch<FUSED, HALFB, A, 0, false, pic::PUSHER_VAY>(x);
+        if (x->pusher == PIC_PUSHER_HC)
+            return x->walls ? push_launch<FUSED, HALFB, A, 0, FUSED, pic::PUSHER_HC>(x)
+                            : push_launch<FUSED, HALFB, A, 0, false, pic::PUSHER_HC>(x);
         if constexpr (FUSED) {
-            if (x->walls) return push_launch<FUSED, HALFB, A, 0, true>(x);
+            if (x->walls) return push_launch<FUSED, HALFB, A, 0, true, pic::PUSHER_BORIS>(x);
         }
         if constexpr (FUSED && std::is_same<A, double>::value) {
             bool cubic = true;
             for (int d = 1; d < D; ++d) cubic = cubic && x->T[d] == x->T[0];
-            if (cubic && x->T[0] == 8) return push_launch<FUSED, HALFB, A, 8, false>(x);
-            if (cubic && x->T[0] == 16) return push_launch<FUSED, HALFB, A, 16, false>(x);
+            if (cubic && x->T[0] == 8) return push_launch<FUSED, HALFB, A, 8, false, pic::PUSHER_BORIS>(x);
+            if (cubic && x->T[0] == 16) return push_launch<FUSED, HALFB, A, 16, false, pic::PUSHER_BORIS>(x);
             if constexpr (D < 3)
-                if (cubic && x->T[0] == 32) return push_launch<FUSED, HALFB, A, 32, false>(x);
+                if (cubic && x->T[0] == 32) return push_launch<FUSED, HALFB, A, 32, false, pic::PUSHER_BORIS>(x);
         }
-        return push_launch<FUSED, HALFB, A, 0, false>(x);
+        return push_launch<FUSED, HALFB, A, 0, false, pic::PUSHER_BORIS>(x);
     }
 
     static pic_status push(pic_ctx *x, bool fused, bool halfb)
@@ -575,6 +588,25 @@ struct Impl {
         return PIC_OK;
     }
 
+    static pic_status filter(pic_ctx *x, int passes)
+    {
+        Params<R> p = params<R>(x);
+        R *tmp = reinterpret_cast<R *>(x->ws + x->L.off_jtmp);
+        dim3 g((unsigned)x->L.pub.tiles_total), b(256);
+        for (int k = 0; k < passes; ++k) {
+            const R *src = k % 2 ? tmp : p.J;
+            R *dst = k % 2 ? p.J : tmp;
+            hipLaunchKernelGGL((pic::k_filter<R, D>), g, b, 0, x->stream, p, src, dst);
+        }
+        if (passes % 2) {
+            const int64_t n = 3 * x->L.pub.cells_total;
+            hipLaunchKernelGGL((pic::k_copy<R>), dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), b, 0,
+                               x->stream, p.J, tmp, n);
+        }
+        HIP_OK(hipGetLastError());
+        return PIC_OK;
+    }
+
     static pic_status unpermute(pic_ctx *x, const void *la, const void *ua, void *lb, void *ub, int64_t stride)
     {
         Params<R> p = params<R>(x);
@@ -645,6 +677,7 @@ pic_status do_deposit(pic_ctx *x, bool unfused) { PIC_DISPATCH(x, deposit(x, unf
 pic_status do_migrate(pic_ctx *x, bool out, bool in, bool sort) { PIC_DISPATCH(x, migrate(x, out, in, sort)); }
 pic_status do_diag(pic_ctx *x, pic_diag *o, bool per_box) { PIC_DISPATCH(x, diag(x, o, per_box)); }
 pic_status do_adjoint(pic_ctx *x, void *a, void *b, void *c, void *d) { PIC_DISPATCH(x, adjoint(x, a, b, c, d)); }
+pic_status do_filter(pic_ctx *x, int passes) { PIC_DISPATCH(x, filter(x, passes)); }
 pic_status do_unpermute(pic_ctx *x, const void *a, const void *b, void *c, void *d, int64_t s)
 {
     PIC_DISPATCH(x, unpermute(x, a, b, c, d, s));
@@ -731,6 +764,8 @@ pic_status pic_init_tiles(const pic_config *cfg, const int64_t *counts, void *wo
     x->persistent = (cfg->options & PIC_OPT_PERSISTENT) != 0;
     x->track = (cfg->options & PIC_OPT_TRACK) != 0;
     x->walls = false;
+    x->pusher = cfg->pusher;
+    x->filter_passes = cfg->filter_passes;
     for (int b = 0; cfg->box_walls && b < cfg->n_boxes; ++b) x->walls = x->walls || (cfg->box_walls[b] & PIC_WALL_X);
     x->graph = nullptr;
     x->graph_steps = 0;
@@ -835,6 +870,7 @@ pic_status pic_step(pic_ctx *x, uint32_t flags)
         if ((st = pic_push_interp(x, flags))) return st;
         if ((st = pic_fdtd_step(x, PIC_TWO_HALF_B))) return st;
         if ((st = pic_deposit_current(x, flags))) return st;
+        if (x->filter_passes && (st = pic_filter_current(x, x->filter_passes))) return st;
         if ((st = pic_fdtd_step(x, PIC_CURL_E_ADD_J))) return st;
         return pic_sort_migrate(x, flags);
     }
@@ -842,8 +878,18 @@ pic_status pic_step(pic_ctx *x, uint32_t flags)
     if ((st = pic_push_interp(x, flags))) return st;
     if ((st = pic_fdtd_step(x, PIC_HALF_B))) return st;
     if ((st = pic_deposit_current(x, flags))) return st;
+    if (x->filter_passes && (st = pic_filter_current(x, x->filter_passes))) return st;
     if ((st = pic_fdtd_step(x, PIC_CURL_E_ADD_J))) return st;
     return pic_sort_migrate(x, flags);
+}
+
+pic_status pic_filter_current(pic_ctx *x, int32_t passes)
+{
+    if (!x) return fail(PIC_E_ARG, "null context");
+    if (passes < 0) return fail(PIC_E_ARG, "passes must be >= 0");
+    if (x->walls) return fail(PIC_E_ARG, "the current filter covers periodic boxes only");
+    if (passes == 0) return PIC_OK;
+    return do_filter(x, passes);
 }
 
 pic_status pic_graph_capture(pic_ctx *x, int32_t nsteps, uint32_t flags)
@@ -932,6 +978,8 @@ pic_status pic_adjoint_step(pic_ctx *x, void *lpos, void *lu, void *lE, void *lB
     if (!x) return fail(PIC_E_ARG, "null context");
     if (!x->track) return fail(PIC_E_STATE, "the context was created without PIC_OPT_TRACK");
     if (x->walls) return fail(PIC_E_ARG, "the adjoint step covers periodic boxes only");
+    if (x->pusher != PIC_PUSHER_BORIS || x->filter_passes)
+        return fail(PIC_E_ARG, "the adjoint step covers the Boris pusher without current filter");
     if (!lpos || !lu || !lE || !lB) return fail(PIC_E_ARG, "adjoint buffers are required");
     if (x->state != 0) return fail(PIC_E_STATE, "the adjoint step must start between steps");
     return do_adjoint(x, lpos, lu, lE, lB);

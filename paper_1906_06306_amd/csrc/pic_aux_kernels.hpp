@@ -14,6 +14,13 @@ __global__ void k_fill(T *p, int64_t n, T v)
         p[i] = v;
 }
 
+template <typename T>
+__global__ void k_copy(T *__restrict__ dst, const T *__restrict__ src, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 // FP64 box field [3][cells] -> working precision, into the global planes.
 template <typename R>
 __global__ void k_load_field(R *dst, int64_t cells_total, int64_t cell0, const double *src, int64_t cells)

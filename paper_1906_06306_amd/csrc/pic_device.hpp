@@ -296,6 +296,83 @@ __device__ __forceinline__ void boris(R u[3], const R e[3], const R b[3], R c, R
     u[2] = u3z * inv_c;
 }
 
+// Lorentz factor of the implicit magnetic rotation: the gamma that solves
+// w1 = w' + (w1/gamma) x tau, from gamma'^2 = 1 + |w'|^2/c^2 and
+// u* = w'.tau/c (Vay 2008; Higuera and Cary 2017).  IEEE square roots in both
+// precisions.
+template <typename R>
+__device__ __forceinline__ R implicit_gamma(const R w[3], const R tau[3], R inv_c)
+{
+    const R g2 = R(1) + (w[0] * w[0] + w[1] * w[1] + w[2] * w[2]) * (inv_c * inv_c);
+    const R us = (w[0] * tau[0] + w[1] * tau[1] + w[2] * tau[2]) * inv_c;
+    const R t2 = tau[0] * tau[0] + tau[1] * tau[1] + tau[2] * tau[2];
+    const R sg = g2 - t2;
+    return sqrt(R(0.5) * (sg + sqrt(sg * sg + R(4) * (t2 + us * us))));
+}
+
+// w <- (w + (w.t) t + w x t) / (1 + |t|^2): the exact rotation of the
+// implicit update.
+template <typename R>
+__device__ __forceinline__ void exact_rotation(R w[3], const R t[3])
+{
+    const R wt = w[0] * t[0] + w[1] * t[1] + w[2] * t[2];
+    const R sf = R(1) / (R(1) + (t[0] * t[0] + t[1] * t[1] + t[2] * t[2]));
+    const R x0 = w[1] * t[2] - w[2] * t[1], x1 = w[2] * t[0] - w[0] * t[2], x2 = w[0] * t[1] - w[1] * t[0];
+    w[0] = sf * (w[0] + wt * t[0] + x0);
+    w[1] = sf * (w[1] + wt * t[1] + x1);
+    w[2] = sf * (w[2] + wt * t[2] + x2);
+}
+
+// Vay pusher (units of App. C, w = c u): the full electric kick and half
+// the magnetic kick with the old velocity, then the other magnetic half with
+// the new velocity, solved exactly.
+template <typename R>
+__device__ __forceinline__ void vay(R u[3], const R e[3], const R b[3], R c, R inv_c, R s)
+{
+    const R k = R(0.5) * s * inv_c;
+    const R tau[3] = {k * b[0], k * b[1], k * b[2]};
+    R w[3] = {c * u[0], c * u[1], c * u[2]};
+    const R ig0 = R(1) / sqrt(R(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    const R v[3] = {w[0] * ig0, w[1] * ig0, w[2] * ig0};
+    w[0] += s * e[0] + (v[1] * tau[2] - v[2] * tau[1]);
+    w[1] += s * e[1] + (v[2] * tau[0] - v[0] * tau[2]);
+    w[2] += s * e[2] + (v[0] * tau[1] - v[1] * tau[0]);
+    const R ig = R(1) / implicit_gamma<R>(w, tau, inv_c);
+    const R t[3] = {tau[0] * ig, tau[1] * ig, tau[2] * ig};
+    exact_rotation<R>(w, t);
+    u[0] = w[0] * inv_c;
+    u[1] = w[1] * inv_c;
+    u[2] = w[2] * inv_c;
+}
+
+// Higuera-Cary pusher: Boris's split with the rotation's Lorentz factor from
+// the implicit relation (volume preserving, exact E x B velocity).
+template <typename R>
+__device__ __forceinline__ void higuera_cary(R u[3], const R e[3], const R b[3], R c, R inv_c, R s)
+{
+    const R hs = R(0.5) * s, k = hs * inv_c;
+    const R eps[3] = {hs * e[0], hs * e[1], hs * e[2]};
+    const R tau[3] = {k * b[0], k * b[1], k * b[2]};
+    R w[3] = {c * u[0] + eps[0], c * u[1] + eps[1], c * u[2] + eps[2]};
+    const R ig = R(1) / implicit_gamma<R>(w, tau, inv_c);
+    const R t[3] = {tau[0] * ig, tau[1] * ig, tau[2] * ig};
+    exact_rotation<R>(w, t);
+    const R x0 = w[1] * t[2] - w[2] * t[1], x1 = w[2] * t[0] - w[0] * t[2], x2 = w[0] * t[1] - w[1] * t[0];
+    u[0] = (w[0] + eps[0] + x0) * inv_c;
+    u[1] = (w[1] + eps[1] + x1) * inv_c;
+    u[2] = (w[2] + eps[2] + x2) * inv_c;
+}
+
+enum : int { PUSHER_BORIS = 0, PUSHER_VAY = 1, PUSHER_HC = 2 };
+
+template <typename R, int PUSHER>
+__device__ __forceinline__ void push_u(R u[3], const R e[3], const R b[3], R c, R inv_c, R s)
+{
+    if constexpr (PUSHER == PUSHER_VAY) vay<R>(u, e, b, c, inv_c, s);
+    else if constexpr (PUSHER == PUSHER_HC) higuera_cary<R>(u, e, b, c, inv_c, s);
+    else boris<R>(u, e, b, c, inv_c, s);
+}
+
 // Eq. (fdX): displacement c u / gamma of u^{n+1/2}, all three components.
 template <typename R>
 __device__ __forceinline__ void displacement(const R u[3], R c, R dv[3])

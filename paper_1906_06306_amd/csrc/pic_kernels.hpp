@@ -142,7 +142,7 @@ __device__ __forceinline__ void compact_chunk(const Params<R> &p, int ts, int64_
 // c0 + j*blockDim + t), so every load and store instruction stays
 // coalesced while U loads per array are in flight; the stable compaction
 // runs once per group.
-template <typename R, int D, bool FUSED, bool HALFB, typename A, int U, int TC, bool WALLS>
+template <typename R, int D, bool FUSED, bool HALFB, typename A, int U, int TC, bool WALLS, int PUSHER>
 __device__ __forceinline__ void push_tile(const Params<R> &p, const int t, unsigned char *smem)
 {
     const TileDesc td = p.tiles[t];
@@ -251,7 +251,7 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int t, unsig
                 if (inside_tile<R, D>(x[j], T)) {
                     R e[3], b[3], dv[3];
                     interp_all<R, D>(sE, cb, sB, fb, x[j], T, e, b);
-                    boris<R>(u[j], e, b, c, inv_c, sq);
+                    push_u<R, PUSHER>(u[j], e, b, c, inv_c, sq);
                     displacement<R>(u[j], c, dv);
 #pragma unroll
                     for (int d = 0; d < D; ++d) x2[j][d] = x[j][d] + dv[d];
@@ -359,17 +359,17 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int t, unsig
 }
 
 // One work-group per tile, tiles dispatched heaviest first.
-template <typename R, int D, bool FUSED, bool HALFB, typename A, int U, int TC, bool WALLS>
+template <typename R, int D, bool FUSED, bool HALFB, typename A, int U, int TC, bool WALLS, int PUSHER>
 __global__ void __launch_bounds__(1024) k_push(Params<R> p)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    push_tile<R, D, FUSED, HALFB, A, U, TC, WALLS>(p, p.order[blockIdx.x], smem);
+    push_tile<R, D, FUSED, HALFB, A, U, TC, WALLS, PUSHER>(p, p.order[blockIdx.x], smem);
 }
 
 // Persistent tile walker: a grid sized to the resident work-groups pulls
 // tiles (heaviest first) from an atomic counter until every tile is taken;
 // every work-group leaves the loop when the counter passes the tile count.
-template <typename R, int D, bool FUSED, bool HALFB, typename A, int U, int TC, bool WALLS>
+template <typename R, int D, bool FUSED, bool HALFB, typename A, int U, int TC, bool WALLS, int PUSHER>
 __global__ void __launch_bounds__(1024) k_push_persistent(Params<R> p)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -380,7 +380,7 @@ __global__ void __launch_bounds__(1024) k_push_persistent(Params<R> p)
         const int k = next;
         __syncthreads();
         if (k >= p.ntiles) break;
-        push_tile<R, D, FUSED, HALFB, A, U, TC, WALLS>(p, p.order[k], smem);
+        push_tile<R, D, FUSED, HALFB, A, U, TC, WALLS, PUSHER>(p, p.order[k], smem);
         __syncthreads();
     }
 }
@@ -536,6 +536,42 @@ __global__ void __launch_bounds__(256) k_field(Params<R> p, R h)
             p.E[N + g] = ey;
             p.E[2 * N + g] = ez;
         }
+    }
+}
+
+// Binomial current filter (the solver table's 3-point digital filter): one
+// pass replaces every value by the (1/4, 1/2, 1/4) average along each grid
+// dimension, i.e. the 3^D stencil of the product weights, periodic inside
+// the box.  src and dst are [3][cells] planes and must differ.
+template <typename R, int D>
+__global__ void __launch_bounds__(256) k_filter(Params<R> p, const R *__restrict__ src, R *__restrict__ dst)
+{
+    const int t = blockIdx.x;
+    const TileDesc td = p.tiles[t];
+    const int T0 = p.T[0], T1 = D > 1 ? p.T[1] : 1, T2 = D > 2 ? p.T[2] : 1;
+    const int ncell = T0 * T1 * T2;
+    const int64_t N = p.cells_total;
+    const int n0 = td.n[0], n1 = td.n[1], n2 = td.n[2];
+    for (int k = threadIdx.x; k < ncell; k += blockDim.x) {
+        const int gx = td.tc[0] * T0 + k % T0;
+        const int gy = D > 1 ? td.tc[1] * T1 + (k / T0) % T1 : 0;
+        const int gz = D > 2 ? td.tc[2] * T2 + k / (T0 * T1) : 0;
+        R acc[3] = {0, 0, 0};
+        for (int oz = (D > 2 ? -1 : 0); oz <= (D > 2 ? 1 : 0); ++oz)
+            for (int oy = (D > 1 ? -1 : 0); oy <= (D > 1 ? 1 : 0); ++oy)
+                for (int ox = -1; ox <= 1; ++ox) {
+                    const R w = (ox ? R(0.25) : R(0.5)) * (D > 1 ? (oy ? R(0.25) : R(0.5)) : R(1)) *
+                                (D > 2 ? (oz ? R(0.25) : R(0.5)) : R(1));
+                    const int64_t g = td.cell0 + wrapi(gx + ox, n0) +
+                                      (int64_t)n0 * (wrapi(gy + oy, n1) + (int64_t)n1 * wrapi(gz + oz, n2));
+                    acc[0] += w * src[g];
+                    acc[1] += w * src[N + g];
+                    acc[2] += w * src[2 * N + g];
+                }
+        const int64_t g = td.cell0 + gx + (int64_t)n0 * (gy + (int64_t)n1 * gz);
+        dst[g] = acc[0];
+        dst[N + g] = acc[1];
+        dst[2 * N + g] = acc[2];
     }
 }
 

@@ -45,7 +45,7 @@ class PicSim:
 
     def __init__(self, boxes, tile, precision: str = "fp32", block: int = 256, capacity_factor: float = 1.25,
                  tile_capacity=None, outbox_capacity: int = 0, options: int = 0, device: str = "cuda:0",
-                 stream=None, walls=False):
+                 stream=None, walls=False, pusher: str = "boris", filter_passes: int = 0):
         if not isinstance(boxes, (list, tuple)):
             boxes = [boxes]
         boxes = [b if isinstance(b, Box) else box_from_plasma(b) for b in boxes]
@@ -92,6 +92,8 @@ class PicSim:
         wl = walls if isinstance(walls, (list, tuple)) else [walls] * self.nb
         self._walls = np.array([L.PIC_WALL_X if w else 0 for w in wl], dtype=np.int32)
         cfg.box_walls = self._walls.ctypes.data if self._walls.any() else None
+        cfg.pusher = {"boris": L.PIC_PUSHER_BORIS, "vay": L.PIC_PUSHER_VAY, "hc": L.PIC_PUSHER_HC}[pusher]
+        cfg.filter_passes = int(filter_passes)
         self.cfg = cfg
         lay = L.PicLayout()
         L.check(lib.pic_query(ctypes.byref(cfg), self._counts.ctypes.data, ctypes.byref(lay)))
@@ -169,6 +171,9 @@ class PicSim:
     def push(self, fused: bool = True, half_b: bool = False):
         flags = (L.PIC_FUSED if fused else 0) | (L.PIC_PUSH_HALF_B if half_b else 0)
         L.check(L.lib().pic_push_interp(self.ctx, flags))
+
+    def filter_current(self, passes: int):
+        L.check(L.lib().pic_filter_current(self.ctx, int(passes)))
 
     def deposit(self):
         L.check(L.lib().pic_deposit_current(self.ctx, 0))
