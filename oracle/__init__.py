@@ -56,7 +56,9 @@ def lib():
             "orc_wrap": (None, [I, P, I64, P]),
             "orc_step": (I, [I, P, Dbl, I, P, P, P, P, P, P, P, P]),
             "orc_step_walls": (I, [I, P, Dbl, I, P, P, P, P, P, P, P, P]),
-            "orc_step_opts": (I, [I, P, Dbl, I, P, P, P, P, P, P, P, P, I, I, I]),
+            "orc_step_opts": (I, [I, P, Dbl, I, P, P, P, P, P, P, P, P, I, I, I, I]),
+            "orc_advance_b4": (None, [I, P, Dbl, P, P]),
+            "orc_advance_e4": (None, [I, P, Dbl, P, P]),
             "orc_vay": (None, [I64, Dbl, Dbl, P, P, P]),
             "orc_hc": (None, [I64, Dbl, Dbl, P, P, P]),
             "orc_filter_binomial": (I, [I, P, I, I, P]),
@@ -101,6 +103,18 @@ def advance_e(D, n, h, B, E):
     """E += h curl-(B) (in place on E)."""
     dims = _dims(n)
     lib().orc_advance_e(D, _p(dims), float(h), _p(B), _p(E))
+
+
+def advance_b4(D, n, h, E, B):
+    """B -= h curl+(E), fourth-order differences (in place on B)."""
+    dims = _dims(n)
+    lib().orc_advance_b4(D, _p(dims), float(h), _p(E), _p(B))
+
+
+def advance_e4(D, n, h, B, E):
+    """E += h curl-(B), fourth-order differences (in place on E)."""
+    dims = _dims(n)
+    lib().orc_advance_e4(D, _p(dims), float(h), _p(B), _p(E))
 
 
 def add_current(n, J, E):
@@ -213,12 +227,14 @@ class State:
         self.s = [float(s.s) for s in plasma.species]
         self.m = [float(s.m) for s in plasma.species]
 
-    def step(self, nsteps: int = 1, walls: bool = False, pusher: int = 0, filter_passes: int = 0):
+    def step(self, nsteps: int = 1, walls: bool = False, pusher: int = 0, filter_passes: int = 0,
+             fdtd_order: int = 2):
         """nsteps full steps; walls=True: conducting, reflecting walls at
         x = 0 and x = n0 (y, z periodic), else periodic everywhere; pusher
-        0 Boris, 1 Vay, 2 Higuera-Cary; filter_passes binomial passes on J."""
-        if pusher or filter_passes:
-            extra = (int(walls), int(pusher), int(filter_passes))
+        0 Boris, 1 Vay, 2 Higuera-Cary; filter_passes binomial passes on J;
+        fdtd_order 2 or 4."""
+        if pusher or filter_passes or fdtd_order != 2:
+            extra = (int(walls), int(pusher), int(filter_passes), int(fdtd_order))
             fn = lambda *a: lib().orc_step_opts(*a, *extra)
         else:
             fn = lib().orc_step_walls if walls else lib().orc_step

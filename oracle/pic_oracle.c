@@ -709,14 +709,83 @@ int orc_filter_binomial(int D, const int n[3], int passes, int nplanes, double *
     return 0;
 }
 
+/* Fourth-order FDTD (the solver table's FDTD4): every difference of the
+ * curls spans the staggered points at +-1/2 and +-3/2 with the weights 9/8
+ * and -1/24, e.g. forward D f(i) = 9/8 (f(i+1) - f(i)) - 1/24 (f(i+2) -
+ * f(i-1)), backward D f(i) = 9/8 (f(i) - f(i-1)) - 1/24 (f(i+1) - f(i-2)).
+ * These are combinations of single- and triple-cell differences, so the
+ * lattice divergences still annihilate the curls. */
+static double d4p(const double *F, const int n[3], int axis, int i, int j, int k)
+{
+    int o[3] = {0, 0, 0};
+    o[axis] = 1;
+    double f0 = F[cell(n, i, j, k)];
+    double f1 = F[cell(n, i + o[0], j + o[1], k + o[2])];
+    double f2 = F[cell(n, i + 2 * o[0], j + 2 * o[1], k + 2 * o[2])];
+    double fm = F[cell(n, i - o[0], j - o[1], k - o[2])];
+    return 9.0 / 8.0 * (f1 - f0) - 1.0 / 24.0 * (f2 - fm);
+}
+
+static double d4m(const double *F, const int n[3], int axis, int i, int j, int k)
+{
+    int o[3] = {0, 0, 0};
+    o[axis] = 1;
+    double f0 = F[cell(n, i, j, k)];
+    double fm = F[cell(n, i - o[0], j - o[1], k - o[2])];
+    double fm2 = F[cell(n, i - 2 * o[0], j - 2 * o[1], k - 2 * o[2])];
+    double f1 = F[cell(n, i + o[0], j + o[1], k + o[2])];
+    return 9.0 / 8.0 * (f0 - fm) - 1.0 / 24.0 * (f1 - fm2);
+}
+
+/* B <- B - h curl+ E with the fourth-order differences. */
+void orc_advance_b4(int D, const int n[3], double h, const double *E, double *B)
+{
+    (void)D;
+    int64_t N = ncells(n);
+    const double *Ex = E, *Ey = E + N, *Ez = E + 2 * N;
+    double *Bx = B, *By = B + N, *Bz = B + 2 * N;
+    for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j)
+            for (int i = 0; i < n[0]; ++i) {
+                int64_t c = cell(n, i, j, k);
+                double cx = d4p(Ez, n, 1, i, j, k) - d4p(Ey, n, 2, i, j, k);
+                double cy = d4p(Ex, n, 2, i, j, k) - d4p(Ez, n, 0, i, j, k);
+                double cz = d4p(Ey, n, 0, i, j, k) - d4p(Ex, n, 1, i, j, k);
+                Bx[c] -= h * cx;
+                By[c] -= h * cy;
+                Bz[c] -= h * cz;
+            }
+}
+
+/* E <- E + h curl- B with the fourth-order differences. */
+void orc_advance_e4(int D, const int n[3], double h, const double *B, double *E)
+{
+    (void)D;
+    int64_t N = ncells(n);
+    const double *Bx = B, *By = B + N, *Bz = B + 2 * N;
+    double *Ex = E, *Ey = E + N, *Ez = E + 2 * N;
+    for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j)
+            for (int i = 0; i < n[0]; ++i) {
+                int64_t c = cell(n, i, j, k);
+                double cx = d4m(Bz, n, 1, i, j, k) - d4m(By, n, 2, i, j, k);
+                double cy = d4m(Bx, n, 2, i, j, k) - d4m(Bz, n, 0, i, j, k);
+                double cz = d4m(By, n, 0, i, j, k) - d4m(Bx, n, 1, i, j, k);
+                Ex[c] += h * cx;
+                Ey[c] += h * cy;
+                Ez[c] += h * cz;
+            }
+}
+
 /* One full step with the options the solver table allows: walls in x
  * (walls = 1, see orc_step_walls), the pusher (0 Boris, 1 Vay,
- * 2 Higuera-Cary) and the number of binomial filter passes applied to the
- * current after comp_curr and before add_cur.  With walls = 0, pusher = 0
- * and passes = 0 it is orc_step; with walls = 1, orc_step_walls.          */
+ * 2 Higuera-Cary), the number of binomial filter passes applied to the
+ * current after comp_curr and before add_cur, and the FDTD order (2, or 4
+ * for FDTD4).  With walls = 0, pusher = 0, passes = 0 and order 2 it is
+ * orc_step; with walls = 1, orc_step_walls.                               */
 int orc_step_opts(int D, const int n[3], double c, int nspecies, const int64_t *n_per,
                   double **x, double **u, const double *q, const double *sgn,
-                  double *E, double *B, double *J, int walls, int pusher, int passes)
+                  double *E, double *B, double *J, int walls, int pusher, int passes, int order)
 {
     if (nspecies < 1) return -1;
     int64_t N = ncells(n);
@@ -734,7 +803,9 @@ int orc_step_opts(int D, const int n[3], double c, int nspecies, const int64_t *
         ok = xold[s] && disp[s];
     }
     if (ok) {
-        orc_advance_b(D, n, 0.5 * c, E, B);                       /* push_half_b1 */
+        void (*adv_b)(int, const int *, double, const double *, double *) = order == 4 ? orc_advance_b4 : orc_advance_b;
+        void (*adv_e)(int, const int *, double, const double *, double *) = order == 4 ? orc_advance_e4 : orc_advance_e;
+        adv_b(D, n, 0.5 * c, E, B);                               /* push_half_b1 */
         for (int s = 0; s < nspecies; ++s) {                       /* interp_em, push */
             int64_t np = n_per[s];
             memcpy(xold[s], x[s], sizeof(double) * (size_t)(D * np));
@@ -745,8 +816,8 @@ int orc_step_opts(int D, const int n[3], double c, int nspecies, const int64_t *
             else orc_boris(np, c, sgn[s], fp, fp + 3 * np, u[s]);
             orc_move(D, np, c, u[s], x[s], disp[s]);
         }
-        orc_advance_b(D, n, 0.5 * c, E, B);                       /* push_half_b2 */
-        orc_advance_e(D, n, c, B, E);                             /* push_e */
+        adv_b(D, n, 0.5 * c, E, B);                               /* push_half_b2 */
+        adv_e(D, n, c, B, E);                                     /* push_e */
         memset(J, 0, sizeof(double) * 3 * (size_t)N);             /* comp_curr */
         for (int s = 0; s < nspecies; ++s) {
             int64_t np = n_per[s];
