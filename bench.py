@@ -86,6 +86,8 @@ def parse():
                     help="turbulence: particle pusher of the timed runs")
     ap.add_argument("--filter-passes", type=int, default=0,
                     help="turbulence: binomial current filter passes per step")
+    ap.add_argument("--fdtd-order", type=int, default=2, choices=[2, 4],
+                    help="turbulence: FDTD2 (App. B) or FDTD4")
     return ap.parse_args()
 
 
@@ -108,22 +110,26 @@ def run_gpu(plasma, args, precision, steps, warmup, tile, profile_only=False):
     from paper_1906_06306_amd.sim import PicSim
 
     sim = PicSim(plasma, tile=(tile, tile), precision=precision, block=args.block,
-                 capacity_factor=args.capacity, pusher=args.pusher, filter_passes=args.filter_passes)
+                 capacity_factor=args.capacity, pusher=args.pusher, filter_passes=args.filter_passes,
+                 fdtd_order=args.fdtd_order)
     stream = torch.cuda.current_stream()
     lib = L.lib()
     ctx = sim.ctx
 
-    flags = L.PIC_FUSED | L.PIC_PUSH_HALF_B
+    halfb = args.fdtd_order == 2
+    flags = L.PIC_FUSED | (L.PIC_PUSH_HALF_B if halfb else 0)
 
     def step(ev=None):
-        # the sequence pic_step(PIC_FUSED | PIC_PUSH_HALF_B) enqueues, with
-        # events around the fused push
+        # the sequence pic_step(flags) enqueues, with events around the
+        # fused push
+        if not halfb:
+            L.check(lib.pic_fdtd_step(ctx, L.PIC_HALF_B))
         if ev is not None:
             ev[0].record(stream)
         L.check(lib.pic_push_interp(ctx, flags))
         if ev is not None:
             ev[1].record(stream)
-        L.check(lib.pic_fdtd_step(ctx, L.PIC_TWO_HALF_B))
+        L.check(lib.pic_fdtd_step(ctx, L.PIC_TWO_HALF_B if halfb else L.PIC_HALF_B))
         L.check(lib.pic_deposit_current(ctx, flags))
         if args.filter_passes:
             L.check(lib.pic_filter_current(ctx, args.filter_passes))
@@ -499,7 +505,7 @@ def main():
                                f"{args.ppc} ppc/species pair plasma, "
                                "theta=0.3, sigma=10, dB/B0=1 (64 modes), c/w_p=3 cells, Courant 0.45",
                    "particles": n_p, "cells": n_c, "tile": tile32, "block": args.block,
-                   "pusher": args.pusher, "filter_passes": args.filter_passes,
+                   "pusher": args.pusher, "filter_passes": args.filter_passes, "fdtd_order": args.fdtd_order,
                    "autotune_ms_per_step": tune32},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

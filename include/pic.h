@@ -123,6 +123,11 @@ typedef struct {
     int32_t pusher;             /* PIC_PUSHER_BORIS (0), _VAY or _HC          */
     int32_t filter_passes;      /* binomial filter passes pic_step applies to
                                    J before add_cur (0 = none)               */
+    int32_t fdtd_order;         /* 2 (or 0): App. B differences; 4: FDTD4 of
+                                   the solver table, every curl difference
+                                   over +-1/2 and +-3/2 with weights 9/8 and
+                                   -1/24 (periodic boxes; pic_step then keeps
+                                   the half B updates out of the push)      */
 } pic_config;
 
 /* pic_config.pusher (the solver table's pushers): the relativistic Boris

@@ -53,7 +53,7 @@ class PicConfig(ctypes.Structure):
         ("tile", I32 * 3), ("block", I32), ("cfl", DBL),
         ("box_cells", P), ("charge", P), ("qm", P), ("mass", P), ("tile_capacity", P),
         ("capacity_factor", DBL), ("outbox_capacity", I32), ("options", U32), ("box_walls", P),
-        ("pusher", I32), ("filter_passes", I32),
+        ("pusher", I32), ("filter_passes", I32), ("fdtd_order", I32),
     ]
 
 

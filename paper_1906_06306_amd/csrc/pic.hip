@@ -79,6 +79,9 @@ pic_status check_config(const pic_config *c)
     if (!(c->cfl > 0.0) || c->cfl * std::sqrt((double)c->dim) > 1.0) return fail(PIC_E_ARG, "cfl must satisfy 0 < c <= 1/sqrt(D)");
     if (c->pusher < PIC_PUSHER_BORIS || c->pusher > PIC_PUSHER_HC) return fail(PIC_E_ARG, "unknown pusher %d", c->pusher);
     if (c->filter_passes < 0) return fail(PIC_E_ARG, "filter_passes must be >= 0");
+    if (c->fdtd_order != 0 && c->fdtd_order != 2 && c->fdtd_order != 4) return fail(PIC_E_ARG, "fdtd_order must be 2 or 4");
+    for (int b = 0; c->fdtd_order == 4 && c->box_walls && b < c->n_boxes; ++b)
+        if (c->box_walls[b] & PIC_WALL_X) return fail(PIC_E_ARG, "FDTD4 covers periodic boxes only");
     for (int b = 0; c->filter_passes > 0 && c->box_walls && b < c->n_boxes; ++b)
         if (c->box_walls[b] & PIC_WALL_X) return fail(PIC_E_ARG, "the current filter covers periodic boxes only");
     int blk = c->block ? c->block : 256;
@@ -260,6 +263,7 @@ struct pic_ctx {
     bool walls;         // some box has conducting walls in x
     int pusher;         // PIC_PUSHER_*
     int filter_passes;  // binomial passes pic_step applies to J
+    int order;          // FDTD order: 2 (App. B) or 4 (FDTD4)
     int n_cu;           // compute units of the device
     hipGraphExec_t graph;   // captured steps, or null
     int graph_steps;
@@ -353,21 +357,27 @@ struct Impl {
                2 * PUSH_UNROLL * pic::MAX_WAVES * sizeof(int);
     }
 
-    static pic_status fdtd(pic_ctx *x, int phase)
+    template <int ORDER>
+    static pic_status fdtd_order(pic_ctx *x, int phase)
     {
         Params<R> p = params<R>(x);
         dim3 g((unsigned)x->L.pub.tiles_total), b(256);
         const R c = (R)x->c;
         switch (phase) {
-        case PIC_HALF_B: hipLaunchKernelGGL((pic::k_field<R, D, 0>), g, b, 0, x->stream, p, R(0.5) * c); break;
-        case PIC_CURL_E: hipLaunchKernelGGL((pic::k_field<R, D, 1>), g, b, 0, x->stream, p, c); break;
-        case PIC_ADD_J: hipLaunchKernelGGL((pic::k_field<R, D, 2>), g, b, 0, x->stream, p, c); break;
-        case PIC_CURL_E_ADD_J: hipLaunchKernelGGL((pic::k_field<R, D, 3>), g, b, 0, x->stream, p, c); break;
-        case PIC_TWO_HALF_B: hipLaunchKernelGGL((pic::k_field<R, D, 4>), g, b, 0, x->stream, p, R(0.5) * c); break;
+        case PIC_HALF_B: hipLaunchKernelGGL((pic::k_field<R, D, 0, ORDER>), g, b, 0, x->stream, p, R(0.5) * c); break;
+        case PIC_CURL_E: hipLaunchKernelGGL((pic::k_field<R, D, 1, ORDER>), g, b, 0, x->stream, p, c); break;
+        case PIC_ADD_J: hipLaunchKernelGGL((pic::k_field<R, D, 2, ORDER>), g, b, 0, x->stream, p, c); break;
+        case PIC_CURL_E_ADD_J: hipLaunchKernelGGL((pic::k_field<R, D, 3, ORDER>), g, b, 0, x->stream, p, c); break;
+        case PIC_TWO_HALF_B: hipLaunchKernelGGL((pic::k_field<R, D, 4, ORDER>), g, b, 0, x->stream, p, R(0.5) * c); break;
         default: return fail(PIC_E_ARG, "unknown fdtd phase %d", phase);
         }
         HIP_OK(hipGetLastError());
         return PIC_OK;
+    }
+
+    static pic_status fdtd(pic_ctx *x, int phase)
+    {
+        return x->order == 4 ? fdtd_order<4>(x, phase) : fdtd_order<2>(x, phase);
     }
 
     template <bool FUSED, bool HALFB, typename A, int TC, bool WALLS, int PUSHER>
@@ -766,6 +776,7 @@ pic_status pic_init_tiles(const pic_config *cfg, const int64_t *counts, void *wo
     x->walls = false;
     x->pusher = cfg->pusher;
     x->filter_passes = cfg->filter_passes;
+    x->order = cfg->fdtd_order == 4 ? 4 : 2;
     for (int b = 0; cfg->box_walls && b < cfg->n_boxes; ++b) x->walls = x->walls || (cfg->box_walls[b] & PIC_WALL_X);
     x->graph = nullptr;
     x->graph_steps = 0;
@@ -824,6 +835,8 @@ pic_status pic_push_interp(pic_ctx *x, uint32_t flags)
     if (!x) return fail(PIC_E_ARG, "null context");
     if (x->state != 0) return fail(PIC_E_STATE, "push called before the previous push was deposited and migrated");
     const bool fused = flags & PIC_FUSED;
+    if (x->order == 4 && (flags & PIC_PUSH_HALF_B))
+        return fail(PIC_E_ARG, "PIC_PUSH_HALF_B applies the second-order half update; use pic_fdtd_step with FDTD4");
     if (x->track && !fused) return fail(PIC_E_ARG, "origin tracking records origins in the fused push only");
     if (x->walls && !fused) return fail(PIC_E_ARG, "boxes with walls need the fused push (PIC_FUSED)");
     pic_status st = do_push(x, fused, (flags & PIC_PUSH_HALF_B) != 0);
@@ -864,6 +877,8 @@ pic_status pic_sort_migrate(pic_ctx *x, uint32_t flags)
 pic_status pic_step(pic_ctx *x, uint32_t flags)
 {
     pic_status st;
+    if (!x) return fail(PIC_E_ARG, "null context");
+    if (x->order == 4) flags &= ~PIC_PUSH_HALF_B;   // the in-LDS half update is second order
     if (flags & PIC_PUSH_HALF_B) {
         // push_half_b1 happens inside the push on its LDS copy of B; both
         // half updates are then applied to the stored B in one pass
@@ -978,8 +993,8 @@ pic_status pic_adjoint_step(pic_ctx *x, void *lpos, void *lu, void *lE, void *lB
     if (!x) return fail(PIC_E_ARG, "null context");
     if (!x->track) return fail(PIC_E_STATE, "the context was created without PIC_OPT_TRACK");
     if (x->walls) return fail(PIC_E_ARG, "the adjoint step covers periodic boxes only");
-    if (x->pusher != PIC_PUSHER_BORIS || x->filter_passes)
-        return fail(PIC_E_ARG, "the adjoint step covers the Boris pusher without current filter");
+    if (x->pusher != PIC_PUSHER_BORIS || x->filter_passes || x->order != 2)
+        return fail(PIC_E_ARG, "the adjoint step covers the Boris pusher and FDTD2 without current filter");
     if (!lpos || !lu || !lE || !lB) return fail(PIC_E_ARG, "adjoint buffers are required");
     if (x->state != 0) return fail(PIC_E_STATE, "the adjoint step must start between steps");
     return do_adjoint(x, lpos, lu, lE, lB);

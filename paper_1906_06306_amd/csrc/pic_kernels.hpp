@@ -469,11 +469,13 @@ __global__ void __launch_bounds__(256) k_fold(Params<R> p)
 
 // ---------------------------------------------------------------- fields
 
+// ORDER 2: the differences of App. B; ORDER 4: the fourth-order differences
+// (FDTD4: weights 9/8 over one cell and -1/24 over three).
 // PHASE 0: B -= h curl+ E.  PHASE 1: E += h curl- B.  PHASE 2: E -= J.
 // PHASE 3: E += h curl- B - J.  PHASE 4: B -= h curl+ E twice (both half
 // updates of Table 1 in one pass, same arithmetic as two PHASE 0 passes).
 // (Eqs. fdB/fdE with the differences of App. B.)
-template <typename R, int D, int PHASE>
+template <typename R, int D, int PHASE, int ORDER = 2>
 __global__ void __launch_bounds__(256) k_field(Params<R> p, R h)
 {
     const int t = blockIdx.x;
@@ -490,7 +492,47 @@ __global__ void __launch_bounds__(256) k_field(Params<R> p, R h)
             return td.cell0 + x + (int64_t)n0 * (y + (int64_t)n1 * z);
         };
         const int64_t g = at(gx, gy, gz);
-        if constexpr (PHASE == 0 || PHASE == 4) {
+        // neighbour along axis a at offset o (periodic), and the differences
+        auto nb = [&](int a, int o) -> int64_t {
+            return a == 0 ? at(wrapi(gx + o, n0), gy, gz) : a == 1 ? at(gx, wrapi(gy + o, n1), gz) : at(gx, gy, wrapi(gz + o, n2));
+        };
+        auto dfw = [&](const R *F, int a) -> R {
+            if (a >= D) return R(0);
+            if constexpr (ORDER == 4)
+                return R(9.0 / 8.0) * (F[nb(a, 1)] - F[g]) - R(1.0 / 24.0) * (F[nb(a, 2)] - F[nb(a, -1)]);
+            return F[nb(a, 1)] - F[g];
+        };
+        auto dbw = [&](const R *F, int a) -> R {
+            if (a >= D) return R(0);
+            if constexpr (ORDER == 4)
+                return R(9.0 / 8.0) * (F[g] - F[nb(a, -1)]) - R(1.0 / 24.0) * (F[nb(a, 1)] - F[nb(a, -2)]);
+            return F[g] - F[nb(a, -1)];
+        };
+        if constexpr (ORDER == 4 && (PHASE == 0 || PHASE == 4)) {
+            const R *Ex = p.E, *Ey = p.E + N, *Ez = p.E + 2 * N;
+            const R cx = dfw(Ez, 1) - dfw(Ey, 2), cy = dfw(Ex, 2) - dfw(Ez, 0), cz = dfw(Ey, 0) - dfw(Ex, 1);
+            R bx = p.B[g] - h * cx, by = p.B[N + g] - h * cy, bz = p.B[2 * N + g] - h * cz;
+            if constexpr (PHASE == 4) {
+                bx -= h * cx;
+                by -= h * cy;
+                bz -= h * cz;
+            }
+            p.B[g] = bx;
+            p.B[N + g] = by;
+            p.B[2 * N + g] = bz;
+        } else if constexpr (ORDER == 4 && (PHASE == 1 || PHASE == 3)) {
+            const R *Bx = p.B, *By = p.B + N, *Bz = p.B + 2 * N;
+            const R cx = dbw(Bz, 1) - dbw(By, 2), cy = dbw(Bx, 2) - dbw(Bz, 0), cz = dbw(By, 0) - dbw(Bx, 1);
+            R ex = p.E[g] + h * cx, ey = p.E[N + g] + h * cy, ez = p.E[2 * N + g] + h * cz;
+            if constexpr (PHASE == 3) {
+                ex -= p.J[g];
+                ey -= p.J[N + g];
+                ez -= p.J[2 * N + g];
+            }
+            p.E[g] = ex;
+            p.E[N + g] = ey;
+            p.E[2 * N + g] = ez;
+        } else if constexpr (PHASE == 0 || PHASE == 4) {
             const R *Ex = p.E, *Ey = p.E + N, *Ez = p.E + 2 * N;
             const int64_t ip = D > 0 ? at(gx + 1 == n0 ? 0 : gx + 1, gy, gz) : g;
             const int64_t jp = D > 1 ? at(gx, gy + 1 == n1 ? 0 : gy + 1, gz) : g;

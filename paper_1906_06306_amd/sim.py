@@ -45,7 +45,7 @@ class PicSim:
 
     def __init__(self, boxes, tile, precision: str = "fp32", block: int = 256, capacity_factor: float = 1.25,
                  tile_capacity=None, outbox_capacity: int = 0, options: int = 0, device: str = "cuda:0",
-                 stream=None, walls=False, pusher: str = "boris", filter_passes: int = 0):
+                 stream=None, walls=False, pusher: str = "boris", filter_passes: int = 0, fdtd_order: int = 2):
         if not isinstance(boxes, (list, tuple)):
             boxes = [boxes]
         boxes = [b if isinstance(b, Box) else box_from_plasma(b) for b in boxes]
@@ -94,6 +94,7 @@ class PicSim:
         cfg.box_walls = self._walls.ctypes.data if self._walls.any() else None
         cfg.pusher = {"boris": L.PIC_PUSHER_BORIS, "vay": L.PIC_PUSHER_VAY, "hc": L.PIC_PUSHER_HC}[pusher]
         cfg.filter_passes = int(filter_passes)
+        cfg.fdtd_order = int(fdtd_order)
         self.cfg = cfg
         lay = L.PicLayout()
         L.check(lib.pic_query(ctypes.byref(cfg), self._counts.ctypes.data, ctypes.byref(lay)))

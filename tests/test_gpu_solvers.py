@@ -48,19 +48,19 @@ CASES = [
 ]
 
 
-def check_step(D, n, T, ppc, prec, pusher, passes, walls, seed):
+def check_step(D, n, T, ppc, prec, pusher, passes, walls, seed, order=2):
     from paper_1906_06306_amd import _lib as L
     from paper_1906_06306_amd.sim import PicSim
     plasma = synth.small_random(D, n, ppc, theta=1.0, seed=seed, field_amp=0.2, q=0.01)
-    print(f"[gpu] D={D} {prec} pusher={pusher} passes={passes} walls={walls}", flush=True)
+    print(f"[gpu] D={D} {prec} pusher={pusher} passes={passes} walls={walls} order={order}", flush=True)
     sim = PicSim(plasma, tile=T, precision=prec, capacity_factor=2.0, options=L.PIC_OPT_TRACK, walls=walls,
-                 pusher=pusher, filter_passes=passes)
+                 pusher=pusher, filter_passes=passes, fdtd_order=order)
     st = common_state(sim, plasma)
     if walls:
         st.hold_walls()
     pre = [slots_in_order(sim, s) for s in range(2)]
     sim.step(1, fused=True, half_b_in_push=True)
-    st.step(1, walls=walls, pusher=PUSHER[pusher], filter_passes=passes)
+    st.step(1, walls=walls, pusher=PUSHER[pusher], filter_passes=passes, fdtd_order=order)
     assert sim.error() == 0
     tol = TOL[prec]
     E, B, J = sim.fields_host(0)
@@ -96,6 +96,48 @@ def test_walls_with_higuera_cary(D, n, T, ppc):
     check_step(D, n, T, ppc, "fp64", "hc", 0, True, 97 + D)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("D,n,T,ppc", CASES)
+def test_fdtd4_step_matches_oracle(D, n, T, ppc, prec):
+    check_step(D, n, T, ppc, prec, "hc", 8, False, 99 + D, order=4)
+
+
+@pytest.mark.parametrize("D,n,T,m", [(1, (32, 1, 1), (16, 1, 1), (5, 0, 0)),
+                                     (3, (16, 12, 8), (8, 4, 4), (2, 3, 1))])
+def test_fdtd4_plane_wave_on_gpu(D, n, T, m):
+    """Vacuum FDTD4 on the GPU follows the exact fourth-order discrete plane
+    wave for 300 steps (FP64, 1e-12)."""
+    import math
+    from paper_1906_06306_amd.sim import PicSim
+    c = 0.45
+    k = np.array([2 * math.pi * m[d] / n[d] if d < D else 0.0 for d in range(3)])
+    kap = 2 * (9.0 / 8.0 * np.sin(k / 2) - 1.0 / 24.0 * np.sin(3 * k / 2))
+    w = 2 * math.asin(c * np.linalg.norm(kap) / 2)
+    e = np.array([0.3, 1.0, -0.4])
+    e = e - kap * (e @ kap) / (kap @ kap)
+    b = c * np.cross(kap, e) / (2 * math.sin(w / 2))
+    stag = np.array([[0.5, 0, 0], [0, 0.5, 0], [0, 0, 0.5], [0, 0.5, 0.5], [0.5, 0, 0.5], [0.5, 0.5, 0]])
+    N = int(np.prod(n))
+    ci = np.arange(N)
+    idx = np.stack([ci % n[0], (ci // n[0]) % n[1], ci // (n[0] * n[1])]).astype(float)
+
+    def wave(t):
+        E = np.stack([e[q] * np.cos(k @ (idx + stag[q][:, None]) - w * t) for q in range(3)])
+        B = np.stack([b[q] * np.cos(k @ (idx + stag[3 + q][:, None]) - w * (t - 0.5)) for q in range(3)])
+        return E, B
+    p = synth.small_random(D, n[:D], 1, seed=1)
+    for sp in p.species:
+        sp.x = sp.x[:, :0].copy()
+        sp.u = sp.u[:, :0].copy()
+    p.E, p.B = wave(0)
+    sim = PicSim(p, tile=T[:D], precision="fp64", fdtd_order=4)
+    sim.step(300, fused=True, half_b_in_push=True)
+    E, B, _ = sim.fields_host(0)
+    Ea, Ba = wave(300)
+    assert rel(E, Ea) < 1e-12 and rel(B, Ba) < 1e-12, (rel(E, Ea), rel(B, Ba))
+    sim.close()
+
+
 @pytest.mark.parametrize("passes", [1, 2, 8])
 def test_filter_entry_point_matches_oracle(passes):
     from paper_1906_06306_amd.sim import PicSim
@@ -126,4 +168,9 @@ def test_rejected_combinations():
     sim.close()
     sim = PicSim(plasma, tile=(8, 8), precision="fp64", walls=True)
     assert L.lib().pic_filter_current(sim.ctx, 2) == L.PIC_E_ARG
+    sim.close()
+    with pytest.raises(L.PicError):
+        PicSim(plasma, tile=(8, 8), precision="fp64", walls=True, fdtd_order=4)
+    sim = PicSim(plasma, tile=(8, 8), precision="fp64", fdtd_order=4)
+    assert L.lib().pic_push_interp(sim.ctx, L.PIC_FUSED | L.PIC_PUSH_HALF_B) == L.PIC_E_ARG
     sim.close()
