@@ -222,7 +222,8 @@ def bench_adjoint(args):
     import synth
     from paper_1906_06306_amd.adjoint import PicWindow
 
-    n, ppc, nsteps, window, tile = 256, 32, 40, 8, (16, 16)
+    # 8^2 tiles: 1,024 work-groups for the 256^2 box (16^2 tiles give only 256)
+    n, ppc, nsteps, window, tile = 256, 32, 40, 8, (8, 8)
     amp, B0 = 0.1, 0.078772
     base = synth.shear(n=n, ppc=ppc, amp=0.0, B0=1.0)
     n_p = base.nparticles

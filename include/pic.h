@@ -220,6 +220,11 @@ typedef struct {
                                 by the last init or sort                    */
     int32_t error_bits;      /* latched device errors (then cleared)         */
     int32_t reserved;
+    double continuity_max;   /* max |rho^{n+1} - rho^n + div- J| on nodes (App.
+                                D's discrete continuity) when exactly one step
+                                separates this call from the previous
+                                diagnostics call, else -1.  J is the last
+                                step's current (after any filter passes). */
 } pic_diag;
 
 typedef struct pic_ctx pic_ctx;

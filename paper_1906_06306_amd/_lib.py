@@ -75,6 +75,7 @@ class PicDiag(ctypes.Structure):
     _fields_ = [
         ("field_energy", DBL), ("kinetic_energy", DBL), ("gauss_max", DBL), ("divb_max", DBL),
         ("charge_total", DBL), ("particles", I64), ("near_face", I64), ("error_bits", I32), ("reserved", I32),
+        ("continuity_max", DBL),
     ]
 
 

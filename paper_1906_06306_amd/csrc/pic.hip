@@ -56,7 +56,7 @@ struct Layout {
     uint64_t off_tmp, off_jblk, off_rblk, off_part, off_ob_pos, off_ob_u, off_ob_dir, off_ob_cnt;
     uint64_t off_tiles, off_charge, off_qm, off_mass, off_order, off_queue;
     uint64_t off_key, off_xl, off_hist;
-    uint64_t off_ob_ids, off_adj_lj, off_adj_eblk, off_adj_bblk, off_ob_boff, off_ob_idx, off_jtmp;
+    uint64_t off_ob_ids, off_adj_lj, off_adj_eblk, off_adj_bblk, off_ob_boff, off_ob_idx, off_jtmp, off_rho_prev;
     int64_t fblk_cells, n_input;
     int64_t jblk_cells, rblk_cells, max_count, max_ntb, nchunks_max, ob_dir_stride;
     std::vector<TileDesc> tiles;
@@ -231,6 +231,7 @@ pic_status make_layout(const pic_config *c, const int64_t *counts, Layout &L)
     L.off_ob_boff = take(tiles * ns * (pic::ncodes<3>() + 1) * 4);
     L.off_ob_idx = take(tiles * ns * obcap * 4);
     L.off_jtmp = take(3 * cells * w);
+    L.off_rho_prev = take(cells * 8);
     L.off_tiles = take(tiles * sizeof(TileDesc));
     L.off_charge = take(nb * ns * w);
     L.off_qm = take(nb * ns * w);
@@ -264,6 +265,8 @@ struct pic_ctx {
     int pusher;         // PIC_PUSHER_*
     int filter_passes;  // binomial passes pic_step applies to J
     int order;          // FDTD order: 2 (App. B) or 4 (FDTD4)
+    int64_t steps;      // completed steps
+    int64_t diag_step;  // steps at the last diagnostics call, or -1
     int n_cu;           // compute units of the device
     hipGraphExec_t graph;   // captured steps, or null
     int graph_steps;
@@ -620,8 +623,11 @@ struct Impl {
     static pic_status unpermute(pic_ctx *x, const void *la, const void *ua, void *lb, void *ub, int64_t stride)
     {
         Params<R> p = params<R>(x);
-        hipLaunchKernelGGL((pic::k_adj_unpermute<R, D>), dim3((unsigned)x->L.pub.tiles_total), dim3(256), 0,
-                           x->stream, p, reinterpret_cast<const R *>(la), reinterpret_cast<const R *>(ua),
+        int64_t maxcap = 1;
+        for (int32_t c : x->L.seg_cap) maxcap = std::max<int64_t>(maxcap, c);
+        const dim3 grid((unsigned)(x->L.pub.tiles_total * x->ns), (unsigned)((maxcap + 255) / 256));
+        hipLaunchKernelGGL((pic::k_adj_unpermute<R, D>), grid, dim3(256), 0, x->stream, p,
+                           reinterpret_cast<const R *>(la), reinterpret_cast<const R *>(ua),
                            reinterpret_cast<R *>(lb), reinterpret_cast<R *>(ub), stride);
         HIP_OK(hipGetLastError());
         return PIC_OK;
@@ -639,7 +645,9 @@ struct Impl {
         if (st) return st;
         dim3 g((unsigned)L.pub.tiles_total);
         hipLaunchKernelGGL((pic::k_diag_tile<R, D>), g, dim3(256), lds, x->stream, p, mass, part, rblk);
-        hipLaunchKernelGGL((pic::k_diag_gauss<R, D>), g, dim3(256), 0, x->stream, p, part, rblk);
+        double *rho_prev = reinterpret_cast<double *>(x->ws + L.off_rho_prev);
+        const int cont_valid = x->diag_step >= 0 && x->steps - x->diag_step == 1;
+        hipLaunchKernelGGL((pic::k_diag_gauss<R, D>), g, dim3(256), 0, x->stream, p, part, rblk, rho_prev, cont_valid);
         HIP_OK(hipGetLastError());
         std::vector<double> h(L.pub.tiles_total * pic::NPART);
         HIP_OK(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, x->stream));
@@ -658,7 +666,16 @@ struct Impl {
             d->gauss_max = std::max(d->gauss_max, o[4]);
             d->charge_total += o[5];
         }
-        for (int k = 0; k < nout; ++k) out[k].near_face = (int64_t)nf;
+        for (int k = 0; k < nout; ++k) {
+            out[k].near_face = (int64_t)nf;
+            out[k].continuity_max = cont_valid ? 0.0 : -1.0;
+        }
+        if (cont_valid)
+            for (int64_t t = 0; t < L.pub.tiles_total; ++t) {
+                pic_diag *d = per_box ? out + L.tiles[t].box : out;
+                d->continuity_max = std::max(d->continuity_max, h[t * pic::NPART + 6]);
+            }
+        x->diag_step = x->steps;
         return PIC_OK;
     }
 };
@@ -777,6 +794,8 @@ pic_status pic_init_tiles(const pic_config *cfg, const int64_t *counts, void *wo
     x->pusher = cfg->pusher;
     x->filter_passes = cfg->filter_passes;
     x->order = cfg->fdtd_order == 4 ? 4 : 2;
+    x->steps = 0;
+    x->diag_step = -1;
     for (int b = 0; cfg->box_walls && b < cfg->n_boxes; ++b) x->walls = x->walls || (cfg->box_walls[b] & PIC_WALL_X);
     x->graph = nullptr;
     x->graph_steps = 0;
@@ -866,11 +885,13 @@ pic_status pic_sort_migrate(pic_ctx *x, uint32_t flags)
     const bool sort = flags & PIC_SORT_CELLS;
     if (x->track && sort) return fail(PIC_E_ARG, "the cell sort does not record origins (PIC_OPT_TRACK)");
     pic_status st;
+    const bool stepped = x->state == 2 || x->state == 3;
     if (x->state == 3) st = do_migrate(x, true, true, sort);        // unfused push: out + in
     else if (x->state == 2) st = do_migrate(x, false, true, sort);  // fused push packed already
     else st = sort ? do_migrate(x, false, false, true) : PIC_OK;    // nothing moved: sort only
     if (st) return st;
     x->state = 0;
+    if (stepped) ++x->steps;
     return PIC_OK;
 }
 
@@ -920,10 +941,12 @@ pic_status pic_graph_capture(pic_ctx *x, int32_t nsteps, uint32_t flags)
     pic_status st = pic_step(x, flags);
     if (st) return st;
     HIP_OK(hipStreamSynchronize(x->stream));
+    const int64_t steps_before = x->steps;   // captured steps do not run now
     HIP_OK(hipStreamBeginCapture(x->stream, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < nsteps && !st; ++k) st = pic_step(x, flags);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(x->stream, &g);
+    x->steps = steps_before;
     if (st) {
         if (g) (void)hipGraphDestroy(g);
         return st;
@@ -943,6 +966,7 @@ pic_status pic_graph_launch(pic_ctx *x)
 {
     if (!x || !x->graph) return fail(PIC_E_STATE, "no captured graph");
     HIP_OK(hipGraphLaunch(x->graph, x->stream));
+    x->steps += x->graph_steps;
     return PIC_OK;
 }
 

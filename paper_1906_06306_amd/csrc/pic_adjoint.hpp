@@ -445,31 +445,26 @@ __global__ void k_adj_neg(R *dst, const R *src, int64_t n)
 }
 
 // Move particle adjoints from the slots of the current state to the slots
-// (or input indices) the particles came from: dst = ids[j].
+// (or input indices) the particles came from: dst = ids[j].  Grid: x over
+// (tile, species) segments, y over chunks of blockDim slots of a segment.
 template <typename R, int D>
 __global__ void __launch_bounds__(256) k_adj_unpermute(Params<R> p, const R *lpos_a, const R *lu_a, R *lpos_b,
                                                        R *lu_b, int64_t stride_b)
 {
-    const int t = blockIdx.x;
+    const int ts = blockIdx.x;
+    const int j = blockIdx.y * blockDim.x + threadIdx.x;
+    const int cnt = p.seg_cnt[ts];
+    if (j >= cnt) return;
     const int64_t cap = p.cap_total;
-    int32_t errs = 0;
-    for (int s = 0; s < p.nspecies; ++s) {
-        const int ts = t * p.nspecies + s;
-        const int64_t so = p.seg_off[ts];
-        const int cnt = p.seg_cnt[ts];
-        for (int j = threadIdx.x; j < cnt; j += blockDim.x) {
-            const int64_t src = so + j, dst = p.ids[so + j];
-            if (dst < 0 || dst >= stride_b) {
-                errs |= ERR_ADJ_MAP;
-                continue;
-            }
-#pragma unroll
-            for (int d = 0; d < D; ++d) lpos_b[d * stride_b + dst] = lpos_a[d * cap + src];
-#pragma unroll
-            for (int m = 0; m < 3; ++m) lu_b[m * stride_b + dst] = lu_a[m * cap + src];
-        }
+    const int64_t src = p.seg_off[ts] + j, dst = p.ids[src];
+    if (dst < 0 || dst >= stride_b) {
+        latch(p.err, ERR_ADJ_MAP);
+        return;
     }
-    if (errs) latch(p.err, errs);
+#pragma unroll
+    for (int d = 0; d < D; ++d) lpos_b[d * stride_b + dst] = lpos_a[d * cap + src];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) lu_b[m * stride_b + dst] = lu_a[m * cap + src];
 }
 
 }  // namespace pic

@@ -314,7 +314,8 @@ __global__ void __launch_bounds__(256) k_diag_tile(Params<R> p, const double *ma
 // Per tile: rho on nodes from the charge blocks of the tile and of its lower
 // neighbours, Gauss residual max |div- E - rho| and total charge.
 template <typename R, int D>
-__global__ void __launch_bounds__(256) k_diag_gauss(Params<R> p, double *part, const double *rblk)
+__global__ void __launch_bounds__(256) k_diag_gauss(Params<R> p, double *part, const double *rblk, double *rho_prev,
+                                                    int cont_valid)
 {
     __shared__ double red[MAX_WAVES];
     const int t = blockIdx.x;
@@ -325,7 +326,7 @@ __global__ void __launch_bounds__(256) k_diag_gauss(Params<R> p, double *part, c
     (void)r2;
     const int64_t N = p.cells_total;
     const int n0 = td.n[0], n1 = td.n[1];
-    double gmax = 0.0, qsum = 0.0;
+    double gmax = 0.0, qsum = 0.0, cmax = 0.0;
     const int ncell = T0 * T1 * T2;
     for (int k = threadIdx.x; k < ncell; k += blockDim.x) {
         const int l[3] = {k % T0, (k / T0) % T1, k / (T0 * T1)};
@@ -360,14 +361,24 @@ __global__ void __launch_bounds__(256) k_diag_gauss(Params<R> p, double *part, c
         double dive = ((double)p.E[g] - (double)p.E[im]) + ((double)p.E[N + g] - (double)p.E[N + jm]) +
                       ((double)p.E[2 * N + g] - (double)p.E[2 * N + km]);
         // the wall plane carries the conductor's surface charge: no Gauss law there
-        if (!((td.walls & 1) && gx == 0)) gmax = fmax(gmax, fabs(dive - rho));
+        const bool wall = (td.walls & 1) && gx == 0;
+        if (!wall) gmax = fmax(gmax, fabs(dive - rho));
         qsum += rho;
+        // discrete continuity against the charge of the previous call
+        if (cont_valid && !wall) {
+            const double divj = ((double)p.J[g] - (double)p.J[im]) + ((double)p.J[N + g] - (double)p.J[N + jm]) +
+                                ((double)p.J[2 * N + g] - (double)p.J[2 * N + km]);
+            cmax = fmax(cmax, fabs(rho - rho_prev[g] + divj));
+        }
+        rho_prev[g] = rho;
     }
     double m = wg_max(gmax, red);
     double s = wg_sum(qsum, red);
+    double cm = wg_max(cmax, red);
     if (threadIdx.x == 0) {
         part[(int64_t)t * NPART + 4] = m;
         part[(int64_t)t * NPART + 5] = s;
+        part[(int64_t)t * NPART + 6] = cm;
     }
 }
 

@@ -283,7 +283,8 @@ class PicSim:
             L.check(code)
         return dict(field_energy=d.field_energy, kinetic_energy=d.kinetic_energy, gauss_max=d.gauss_max,
                     divb_max=d.divb_max, charge_total=d.charge_total, particles=d.particles,
-                    near_face=d.near_face, error_bits=d.error_bits, status=code)
+                    near_face=d.near_face, error_bits=d.error_bits, continuity_max=d.continuity_max,
+                    status=code)
 
     def box_diagnostics(self) -> list:
         """Diagnostics of every box (FP64), one dict per box."""
@@ -293,7 +294,7 @@ class PicSim:
             L.check(code)
         return [dict(field_energy=d.field_energy, kinetic_energy=d.kinetic_energy, gauss_max=d.gauss_max,
                      divb_max=d.divb_max, charge_total=d.charge_total, particles=d.particles,
-                     error_bits=d.error_bits, status=code) for d in arr]
+                     error_bits=d.error_bits, continuity_max=d.continuity_max, status=code) for d in arr]
 
     def close(self):
         if getattr(self, "ctx", None):

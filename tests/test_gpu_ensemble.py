@@ -93,3 +93,26 @@ def test_diagnostics_match_oracle(D, n, T, ppc):
     b = np.abs(st.div_b()).max()
     assert abs(d["divb_max"] - b) < 1e-12 * max(b, np.abs(st.B).max())
     sim.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+@pytest.mark.parametrize("D,n,T,ppc", [(1, (96, 1, 1), (16, 1, 1), 24), (2, (48, 32, 1), (16, 16, 1), 6),
+                                      (3, (16, 16, 8), (8, 8, 4), 2)])
+def test_continuity_residual(D, n, T, ppc, prec, tol):
+    """The diagnostics' discrete continuity residual max |rho^{n+1} - rho^n +
+    div- J| vanishes to round-off one step after a diagnostics call (App. D's
+    charge conservation, measured on the GPU in FP64 from the stored state),
+    and is reported as -1 when the calls are not one step apart."""
+    from paper_1906_06306_amd.sim import PicSim
+    plasma = synth.small_random(D, n, ppc, seed=85 + D, field_amp=0.05, q=0.01)
+    sim = PicSim(plasma, tile=T, precision=prec)
+    assert sim.diagnostics()["continuity_max"] == -1.0
+    sim.step(1, fused=True, half_b_in_push=True)
+    d = sim.diagnostics()
+    qscale = 0.01 * ppc
+    assert 0.0 <= d["continuity_max"] < tol * qscale, d["continuity_max"]
+    sim.step(2, fused=True, half_b_in_push=True)
+    assert sim.diagnostics()["continuity_max"] == -1.0
+    sim.step(1, fused=True, half_b_in_push=True)
+    assert 0.0 <= sim.diagnostics()["continuity_max"] < tol * qscale
+    sim.close()
