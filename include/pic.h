@@ -128,6 +128,9 @@ typedef struct {
                                    over +-1/2 and +-3/2 with weights 9/8 and
                                    -1/24 (periodic boxes; pic_step then keeps
                                    the half B updates out of the push)      */
+    int64_t inject_max;         /* largest batch pic_inject takes (sizes the
+                                   binning scratch); 0 = the largest initial
+                                   (box, species) count                      */
 } pic_config;
 
 /* pic_config.pusher (the solver table's pushers): the relativistic Boris
@@ -285,6 +288,19 @@ pic_status pic_step(pic_ctx *ctx, uint32_t flags);
  * if the context is bound to the default (null) stream, which cannot be
  * captured. */
 pic_status pic_graph_capture(pic_ctx *ctx, int32_t nsteps, uint32_t flags);
+
+/* Particle creation in tiles (the shock setup's injector adds plasma every
+ * step from a receding wall, Sect. 5.2): append count particles of one box
+ * and species, FP64 global positions pos [dim][count] and four-velocities
+ * u [3][count] (device pointers; the caller draws them), binned into their
+ * tiles exactly as pic_init_tiles does and placed after the particles a tile
+ * already holds (input order kept).  Between steps only.  A full segment
+ * latches PIC_E_CAPACITY; a position outside the box PIC_E_OUT_OF_TILE.
+ * Injected particles carry origin id -1 (the reverse-mode calls do not cover
+ * creation).  Electrons and positrons placed on the same positions add no
+ * net charge, so Gauss's law is kept. */
+pic_status pic_inject(pic_ctx *ctx, int32_t box, int32_t species, int64_t count, const double *pos,
+                      const double *u);
 
 /* The solver table's 3-point binomial current filter: passes times, J <-
  * the (1/4, 1/2, 1/4) average along every grid dimension (the 3^D product

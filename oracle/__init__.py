@@ -252,6 +252,12 @@ class State:
             if rc != 0:
                 raise MemoryError("oracle step could not allocate scratch")
 
+    def append(self, species: int, x, u):
+        """Add particles (global x (D, k), u (3, k)) after the existing ones:
+        particle creation, the oracle side of the injector."""
+        self.x[species] = np.ascontiguousarray(np.concatenate([self.x[species], _f64(x)], axis=1))
+        self.u[species] = np.ascontiguousarray(np.concatenate([self.u[species], _f64(u)], axis=1))
+
     def copy(self):
         other = State.__new__(State)
         other.D, other.n, other.c = self.D, self.n, self.c

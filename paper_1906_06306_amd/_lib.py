@@ -36,7 +36,7 @@ PIC_PUSHER_VAY = 1
 PIC_PUSHER_HC = 2
 
 EXPORTS = ["pic_query", "pic_init_tiles", "pic_fdtd_step", "pic_push_interp", "pic_deposit_current",
-           "pic_sort_migrate", "pic_step", "pic_filter_current", "pic_graph_capture", "pic_graph_launch", "pic_error",
+           "pic_sort_migrate", "pic_step", "pic_inject", "pic_filter_current", "pic_graph_capture", "pic_graph_launch", "pic_error",
            "pic_diagnostics", "pic_diagnostics_boxes", "pic_adjoint_unpermute", "pic_adjoint_step", "pic_destroy", "pic_last_error"]
 
 P = ctypes.c_void_p
@@ -53,7 +53,7 @@ class PicConfig(ctypes.Structure):
         ("tile", I32 * 3), ("block", I32), ("cfl", DBL),
         ("box_cells", P), ("charge", P), ("qm", P), ("mass", P), ("tile_capacity", P),
         ("capacity_factor", DBL), ("outbox_capacity", I32), ("options", U32), ("box_walls", P),
-        ("pusher", I32), ("filter_passes", I32), ("fdtd_order", I32),
+        ("pusher", I32), ("filter_passes", I32), ("fdtd_order", I32), ("inject_max", I64),
     ]
 
 
@@ -104,6 +104,7 @@ def lib():
             "pic_sort_migrate": [P, U32],
             "pic_step": [P, U32],
             "pic_filter_current": [P, I32],
+            "pic_inject": [P, I32, I32, I64, P, P],
             "pic_graph_capture": [P, I32, U32],
             "pic_graph_launch": [P],
             "pic_error": [P],

@@ -143,6 +143,7 @@ pic_status make_layout(const pic_config *c, const int64_t *counts, Layout &L)
         for (int s = 0; s < ns; ++s) {
             if (counts[b * ns + s] < 0) return fail(PIC_E_ARG, "negative particle count");
             L.max_count = std::max(L.max_count, counts[b * ns + s]);
+            L.max_count = std::max<int64_t>(L.max_count, c->inject_max);
         }
     }
     if (L.max_ntb > 32768) return fail(PIC_E_ARG, "a box has %lld tiles; at most 32768 are supported", (long long)L.max_ntb);
@@ -492,7 +493,11 @@ struct Impl {
         return PIC_OK;
     }
 
-    static pic_status init(pic_ctx *x, const int64_t *counts, const pic_init_data *in)
+    // Bin count FP64 particles of (box b, species s) into their tiles and
+    // append them to the segments (after the particles already there, input
+    // order kept inside a tile); origin ids id_base + i, or -1 if id_base < 0.
+    static pic_status bin_species(pic_ctx *x, int b, int s, int64_t count, const double *pos, const double *u,
+                                  int64_t id_base)
     {
         Params<R> p = params<R>(x);
         const Layout &L = x->L;
@@ -500,6 +505,45 @@ struct Impl {
         int32_t *key = reinterpret_cast<int32_t *>(ws + L.off_key);
         R *xl = reinterpret_cast<R *>(ws + L.off_xl);
         int32_t *hist = reinterpret_cast<int32_t *>(ws + L.off_hist);
+        const TileDesc &t0 = L.tiles[L.box_tile0[b]];
+        pic::BinGeom g{};
+        for (int d = 0; d < 3; ++d) {
+            g.n[d] = t0.n[d];
+            g.T[d] = x->T[d];
+            g.nt[d] = t0.nt[d];
+        }
+        g.ntb = t0.nt[0] * t0.nt[1] * t0.nt[2];
+        g.count = count;
+        g.nchunks = (int32_t)std::min<int64_t>(L.nchunks_max, std::max<int64_t>(1, (count + 4095) / 4096));
+        g.chunk = (int32_t)((count + g.nchunks - 1) / g.nchunks);
+        g.id_base = id_base;
+        g.walls = L.tiles[L.box_tile0[b]].walls != 0 || L.tiles[L.box_tile0[b] + t0.nt[0] - 1].walls != 0;
+        int kgrid = (int)std::min<int64_t>((count + 255) / 256, 16384);
+        hipLaunchKernelGGL((pic::k_bin_keys<R, D>), dim3(kgrid), dim3(256), 0, x->stream, g, pos, key, xl, p.err,
+                           p.nearface);
+        size_t lds = (size_t)g.ntb * sizeof(int);
+        pic_status st = set_lds(pic::k_bin_hist, lds);
+        if (st) return st;
+        hipLaunchKernelGGL(pic::k_bin_hist, dim3(g.nchunks), dim3(256), lds, x->stream, g, key, hist);
+        hipLaunchKernelGGL(pic::k_bin_scan, dim3((g.ntb + 255) / 256), dim3(256), 0, x->stream, g, hist, p.seg_cnt,
+                           p.seg_cap, (int)L.box_tile0[b], x->ns, s, p.err);
+        st = set_lds(pic::k_bin_scatter<R, D>, lds);
+        if (st) return st;
+        hipLaunchKernelGGL((pic::k_bin_scatter<R, D>), dim3(g.nchunks), dim3(64), lds, x->stream, g, key, xl, u, hist, p,
+                           (int)L.box_tile0[b], s);
+        HIP_OK(hipGetLastError());
+        return PIC_OK;
+    }
+
+    static pic_status inject(pic_ctx *x, int b, int s, int64_t count, const double *pos, const double *u)
+    {
+        return bin_species(x, b, s, count, pos, u, -1);
+    }
+
+    static pic_status init(pic_ctx *x, const int64_t *counts, const pic_init_data *in)
+    {
+        Params<R> p = params<R>(x);
+        const Layout &L = x->L;
         pic_status st = fill<int32_t>(x, p.seg_cnt, L.pub.tiles_total * x->ns, 0);
         if (!st) st = fill<int32_t>(x, p.ob_cnt, L.pub.tiles_total * x->ns, 0);
         if (!st) st = fill<R>(x, p.J, 3 * L.pub.cells_total, R(0));
@@ -525,32 +569,8 @@ struct Impl {
                 if (count == 0) continue;
                 if (!in->pos || !in->u || !in->pos[b * x->ns + s] || !in->u[b * x->ns + s])
                     return fail(PIC_E_ARG, "missing particle data for box %d species %d", b, s);
-                pic::BinGeom g{};
-                for (int d = 0; d < 3; ++d) {
-                    g.n[d] = t0.n[d];
-                    g.T[d] = x->T[d];
-                    g.nt[d] = t0.nt[d];
-                }
-                g.ntb = t0.nt[0] * t0.nt[1] * t0.nt[2];
-                g.count = count;
-                g.nchunks = (int32_t)std::min<int64_t>(L.nchunks_max, std::max<int64_t>(1, (count + 4095) / 4096));
-                g.chunk = (int32_t)((count + g.nchunks - 1) / g.nchunks);
-                g.id_base = id_base - count;
-                g.walls = L.tiles[L.box_tile0[b]].walls != 0 || L.tiles[L.box_tile0[b] + t0.nt[0] - 1].walls != 0;
-                int kgrid = (int)std::min<int64_t>((count + 255) / 256, 16384);
-                hipLaunchKernelGGL((pic::k_bin_keys<R, D>), dim3(kgrid), dim3(256), 0, x->stream, g, in->pos[b * x->ns + s],
-                                   key, xl, p.err, p.nearface);
-                size_t lds = (size_t)g.ntb * sizeof(int);
-                st = set_lds(pic::k_bin_hist, lds);
+                st = bin_species(x, b, s, count, in->pos[b * x->ns + s], in->u[b * x->ns + s], id_base - count);
                 if (st) return st;
-                hipLaunchKernelGGL(pic::k_bin_hist, dim3(g.nchunks), dim3(256), lds, x->stream, g, key, hist);
-                hipLaunchKernelGGL(pic::k_bin_scan, dim3((g.ntb + 255) / 256), dim3(256), 0, x->stream, g, hist, p.seg_cnt,
-                                   p.seg_cap, (int)L.box_tile0[b], x->ns, s, p.err);
-                st = set_lds(pic::k_bin_scatter<R, D>, lds);
-                if (st) return st;
-                hipLaunchKernelGGL((pic::k_bin_scatter<R, D>), dim3(g.nchunks), dim3(64), lds, x->stream, g, key, xl,
-                                   in->u[b * x->ns + s], hist, p, (int)L.box_tile0[b], s);
-                HIP_OK(hipGetLastError());
             }
         }
         if (x->walls) {
@@ -705,6 +725,10 @@ pic_status do_migrate(pic_ctx *x, bool out, bool in, bool sort) { PIC_DISPATCH(x
 pic_status do_diag(pic_ctx *x, pic_diag *o, bool per_box) { PIC_DISPATCH(x, diag(x, o, per_box)); }
 pic_status do_adjoint(pic_ctx *x, void *a, void *b, void *c, void *d) { PIC_DISPATCH(x, adjoint(x, a, b, c, d)); }
 pic_status do_filter(pic_ctx *x, int passes) { PIC_DISPATCH(x, filter(x, passes)); }
+pic_status do_inject(pic_ctx *x, int b, int s, int64_t n, const double *pos, const double *u)
+{
+    PIC_DISPATCH(x, inject(x, b, s, n, pos, u));
+}
 pic_status do_unpermute(pic_ctx *x, const void *a, const void *b, void *c, void *d, int64_t s)
 {
     PIC_DISPATCH(x, unpermute(x, a, b, c, d, s));
@@ -917,6 +941,18 @@ pic_status pic_step(pic_ctx *x, uint32_t flags)
     if (x->filter_passes && (st = pic_filter_current(x, x->filter_passes))) return st;
     if ((st = pic_fdtd_step(x, PIC_CURL_E_ADD_J))) return st;
     return pic_sort_migrate(x, flags);
+}
+
+pic_status pic_inject(pic_ctx *x, int32_t box, int32_t species, int64_t count, const double *pos, const double *u)
+{
+    if (!x) return fail(PIC_E_ARG, "null context");
+    if (x->state != 0) return fail(PIC_E_STATE, "inject between steps");
+    if (box < 0 || box >= x->nb || species < 0 || species >= x->ns) return fail(PIC_E_ARG, "box or species out of range");
+    if (count < 0 || count > x->L.max_count)
+        return fail(PIC_E_ARG, "a batch holds at most %lld particles (pic_config.inject_max)", (long long)x->L.max_count);
+    if (count == 0) return PIC_OK;
+    if (!pos || !u) return fail(PIC_E_ARG, "pos and u are required");
+    return do_inject(x, box, species, count, pos, u);
 }
 
 pic_status pic_filter_current(pic_ctx *x, int32_t passes)

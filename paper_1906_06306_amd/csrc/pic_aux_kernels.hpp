@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(64) k_bin_scatter(BinGeom g, const int32_t *ke
                 for (int d = 0; d < D; ++d) p.pos[d * cap + dst] = xl[d * g.count + i];
 #pragma unroll
                 for (int mm = 0; mm < 3; ++mm) p.u[mm * cap + dst] = (R)u64[mm * g.count + i];
-                if (p.ids) p.ids[dst] = (int32_t)(g.id_base + i);   // index in the concatenated input
+                if (p.ids) p.ids[dst] = g.id_base < 0 ? -1 : (int32_t)(g.id_base + i);   // index in the concatenated input
             }
         }
     }

@@ -45,7 +45,8 @@ class PicSim:
 
     def __init__(self, boxes, tile, precision: str = "fp32", block: int = 256, capacity_factor: float = 1.25,
                  tile_capacity=None, outbox_capacity: int = 0, options: int = 0, device: str = "cuda:0",
-                 stream=None, walls=False, pusher: str = "boris", filter_passes: int = 0, fdtd_order: int = 2):
+                 stream=None, walls=False, pusher: str = "boris", filter_passes: int = 0, fdtd_order: int = 2,
+                 inject_max: int = 0):
         if not isinstance(boxes, (list, tuple)):
             boxes = [boxes]
         boxes = [b if isinstance(b, Box) else box_from_plasma(b) for b in boxes]
@@ -95,6 +96,7 @@ class PicSim:
         cfg.pusher = {"boris": L.PIC_PUSHER_BORIS, "vay": L.PIC_PUSHER_VAY, "hc": L.PIC_PUSHER_HC}[pusher]
         cfg.filter_passes = int(filter_passes)
         cfg.fdtd_order = int(fdtd_order)
+        cfg.inject_max = int(inject_max)
         self.cfg = cfg
         lay = L.PicLayout()
         L.check(lib.pic_query(ctypes.byref(cfg), self._counts.ctypes.data, ctypes.byref(lay)))
@@ -172,6 +174,15 @@ class PicSim:
     def push(self, fused: bool = True, half_b: bool = False):
         flags = (L.PIC_FUSED if fused else 0) | (L.PIC_PUSH_HALF_B if half_b else 0)
         L.check(L.lib().pic_push_interp(self.ctx, flags))
+
+    def inject(self, box: int, species: int, pos, u):
+        """Append particles (FP64 global positions (D, k), four-velocities
+        (3, k), numpy or tensors) to box `box`, species `species`."""
+        pt = _dev64(pos, self.device)
+        ut = _dev64(u, self.device)
+        torch.cuda.current_stream(self.device).synchronize()   # inputs resident before the library's stream reads them
+        L.check(L.lib().pic_inject(self.ctx, int(box), int(species), int(pt.shape[1]), pt.data_ptr(), ut.data_ptr()))
+        self.stream.synchronize()                              # keep the inputs alive until binned
 
     def filter_current(self, passes: int):
         L.check(L.lib().pic_filter_current(self.ctx, int(passes)))

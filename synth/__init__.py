@@ -368,6 +368,43 @@ def shear_tensors(base: Plasma, A, B0):
     return E, B, parts
 
 
+class RecedingInjector:
+    """Plasma injected from a wall receding at the speed of light (the
+    shock setup of Sect. 5.2): at step k the injector face moves from x0 +
+    k c to x0 + (k+1) c, and the slab between the two faces (all y, z) is
+    filled with ppc particles per unit cell volume per species, drawn
+    uniformly in the slab, moving towards -x with Lorentz factor gamma
+    (theta boosted); each positron sits on an electron.  Deterministic per
+    (seed, step).  The slab stops at the box end x = n0."""
+
+    def __init__(self, n: tuple, ppc: int, gamma: float, theta: float, c: float = 0.45, x0: float = 0.0,
+                 seed: int = BASE_SEED + 6):
+        self.n = tuple(n)
+        self.D = len(n)
+        self.ppc, self.gamma, self.theta, self.c, self.x0, self.seed = ppc, gamma, theta, c, x0, seed
+        self._carry = 0.0
+
+    def batch(self, step: int):
+        """(x (D, k), u_e (3, k), u_p (3, k)) of the slab of this step
+        (steps must be asked in order: the fractional count carries over)."""
+        rng = np.random.default_rng([self.seed, step])
+        lo = min(self.x0 + step * self.c, self.n[0])
+        hi = min(self.x0 + (step + 1) * self.c, self.n[0])
+        area = float(np.prod(self.n[1:])) if self.D > 1 else 1.0
+        want = self.ppc * (hi - lo) * area + self._carry
+        k = int(np.floor(want))
+        self._carry = want - k
+        x = np.empty((self.D, k))
+        x[0] = lo + (hi - lo) * rng.random(k)
+        x[0] = np.minimum(x[0], np.nextafter(self.n[0], 0.0))
+        for d in range(1, self.D):
+            x[d] = self.n[d] * rng.random(k)
+            x[d] = np.where(x[d] >= self.n[d], 0.0, x[d])
+        ue = boost_x(rng, sample_mj(rng, self.theta, k), self.gamma, -1.0)
+        up = boost_x(rng, sample_mj(rng, self.theta, k), self.gamma, -1.0)
+        return x, ue, up
+
+
 def small_random(D: int, n: tuple, ppc: int, theta: float = 0.3, c: float = 0.45,
                  field_amp: float = 0.05, seed: int = 12345, q: float = 1e-3) -> Plasma:
     """A generic small test state: thermal pair plasma plus random E and B of
