@@ -82,6 +82,8 @@ def parse():
                          "1024x128x128, 4:1 uneven tiles, per-tile and persistent push; ensemble: 64 "
                          "independent 2D3V boxes stepped together (autotuned tile, persistent walker, graph)")
     ap.add_argument("--fd", action="store_true", help="shear-adjoint: also central differences of the FP64 forward")
+    ap.add_argument("--shock-blocks", type=lambda v: [int(b) for b in v.split(",")], default=[256, 512, 1024],
+                    help="shock: work-group sizes of the per-tile push to try")
     ap.add_argument("--pusher", default="boris", choices=["boris", "vay", "hc"],
                     help="turbulence: particle pusher of the timed runs")
     ap.add_argument("--filter-passes", type=int, default=0,
@@ -305,10 +307,13 @@ def bench_shock(args):
     T = (8, 8, 8)
     log(f"generated {n_p} particles in {time.perf_counter() - t0:.1f}s")
     results = {}
-    for name, opts in (("per_tile", 0), ("persistent", L.PIC_OPT_PERSISTENT)):
+    runs = [(f"per_tile_b{b}", 0, b) for b in args.shock_blocks] + [("persistent", L.PIC_OPT_PERSISTENT, None)]
+    for name, opts, blk in runs:
+        if blk is None:   # the persistent walker at the best per-tile block size
+            blk = int(min((k for k in results), key=lambda k: results[k]["seconds"]).split("_b")[1])
         # segment capacities from the initial per-tile counts (4:1 uneven)
         sim = PicSim(plasma, tile=T, precision="fp32", tile_capacity="auto", capacity_factor=1.25, options=opts,
-                     walls=True)
+                     walls=True, block=blk)
         log(f"{name}: initialised")
         stream = torch.cuda.current_stream()
         lib = L.lib()
@@ -333,7 +338,7 @@ def bench_shock(args):
         sim.close()
         del sim
         torch.cuda.empty_cache()
-        results[name] = dict(seconds=dt, push_ms=push_ms, diag=diag)
+        results[name] = dict(seconds=dt, push_ms=push_ms, diag=diag, block=blk)
         log(f"{name}: {dt / args.steps * 1e3:.3f} ms/step, push {push_ms:.3f} ms, status {diag['status']}")
     best = min(results, key=lambda k: results[k]["seconds"])
     r = results[best]
@@ -352,8 +357,8 @@ def bench_shock(args):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_push<float,3,fused,walls>",
                      "push_ms": r["push_ms"], "algorithmic_bytes_per_launch": pb},
         "step_roofline_frac": algorithmic_bytes(D, 4, n_p, n_c) * value / n_p / 1e9 / HBM_PEAK_GBS,
-        "per_tile_ms_per_step": results["per_tile"]["seconds"] / args.steps * 1e3,
-        "persistent_ms_per_step": results["persistent"]["seconds"] / args.steps * 1e3,
+        "ms_per_step_by_run": {k: v["seconds"] / args.steps * 1e3 for k, v in results.items()},
+        "block": r["block"],
         "status": {k: v["diag"]["status"] for k, v in results.items()},
     }
     print(json.dumps(out), flush=True)
