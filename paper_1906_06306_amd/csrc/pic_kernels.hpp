@@ -16,17 +16,24 @@ constexpr int MAX_WAVES = 16;
 // two halves alternate by `parity`, so one barrier per call suffices.
 __device__ __forceinline__ int wg_scan_flag(bool flag, int *sTot, int parity, int &total)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
+    // the wave index, wave count and per-wave totals are uniform: keep them
+    // scalar (unrolled over the largest wave count, immediate LDS offsets)
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = __builtin_amdgcn_readfirstlane(blockDim.x >> 6);
     unsigned long long m = __ballot(flag);
     int below = lanes_below(m);
     int *tot = sTot + parity * MAX_WAVES;
     if (lane == 0) tot[wave] = __popcll(m);
     __syncthreads();
     int off = 0, all = 0;
-    for (int w = 0; w < nw; ++w) {
-        int v = tot[w];
-        off += w < wave ? v : 0;
-        all += v;
+#pragma unroll
+    for (int w = 0; w < MAX_WAVES; ++w) {
+        if (w < nw) {
+            const int v = __builtin_amdgcn_readfirstlane(tot[w]);
+            off += w < wave ? v : 0;
+            all += v;
+        }
     }
     total = all;
     return off + below;
@@ -38,7 +45,11 @@ __device__ __forceinline__ int wg_scan_flag(bool flag, int *sTot, int parity, in
 template <int U>
 __device__ __forceinline__ int wg_scan_flags(const bool f[U], int *sTot, int parity, int pre[U])
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
+    // the wave index, wave count and per-wave totals are uniform: keep them
+    // scalar (unrolled over the largest wave count, immediate LDS offsets)
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = __builtin_amdgcn_readfirstlane(blockDim.x >> 6);
     int *tot = sTot + parity * U * MAX_WAVES;
     int below[U];
 #pragma unroll
@@ -51,10 +62,16 @@ __device__ __forceinline__ int wg_scan_flags(const bool f[U], int *sTot, int par
     int run = 0;
 #pragma unroll
     for (int j = 0; j < U; ++j) {
-        for (int w = 0; w < nw; ++w) {
-            if (w == wave) pre[j] = run + below[j];
-            run += tot[j * MAX_WAVES + w];
+        int base = 0;
+#pragma unroll
+        for (int w = 0; w < MAX_WAVES; ++w) {
+            if (w < nw) {
+                const int v = __builtin_amdgcn_readfirstlane(tot[j * MAX_WAVES + w]);
+                base = w == wave ? run : base;
+                run += v;
+            }
         }
+        pre[j] = base + below[j];
     }
     return run;
 }
