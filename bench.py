@@ -57,7 +57,9 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: the workload's run length: turbulence 500, "
+                         "ensemble 100, shock 50)")
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=1024, help="cells per side")
     ap.add_argument("--ppc", type=int, default=16, help="particles per cell per species")
@@ -90,7 +92,10 @@ def parse():
                     help="turbulence: binomial current filter passes per step")
     ap.add_argument("--fdtd-order", type=int, default=2, choices=[2, 4],
                     help="turbulence: FDTD2 (App. B) or FDTD4")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.steps is None:
+        args.steps = {"turbulence": 500, "ensemble": 100}.get(args.workload, 50)
+    return args
 
 
 def algorithmic_bytes(D, w, n_particles, n_cells):

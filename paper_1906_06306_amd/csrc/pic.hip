@@ -28,6 +28,10 @@ using pic::TileDesc;
 
 namespace {
 
+// largest segment or outbox capacity: the push addresses slots by 32-bit
+// byte offsets from the segment's base, 8 * 2^28 bytes at FP64
+constexpr int64_t MAX_SLOTS = int64_t(1) << 28;
+
 thread_local std::string g_last_error;
 
 pic_status fail(pic_status code, const char *fmt, ...)
@@ -168,7 +172,8 @@ pic_status make_layout(const pic_config *c, const int64_t *counts, Layout &L)
                 double expect = (double)counts[b * ns + s] / (double)ntb;
                 cap = round_up((int64_t)std::ceil(factor * expect) + 64, group);
             }
-            if (cap > INT32_MAX / 2) return fail(PIC_E_ARG, "segment capacity too large");
+            // the push addresses a segment's slots by 32-bit byte offsets
+            if (cap > MAX_SLOTS) return fail(PIC_E_ARG, "segment capacity too large (at most 2^28 slots)");
             L.seg_off[t * ns + s] = cap_total;
             L.seg_cap[t * ns + s] = (int32_t)cap;
             cap_total += cap;
@@ -226,7 +231,8 @@ pic_status make_layout(const pic_config *c, const int64_t *counts, Layout &L)
     L.off_part = take(tiles * pic::NPART * 8);
     L.off_ob_pos = take(tiles * ns * obcap * D * w);
     L.off_ob_u = take(tiles * ns * obcap * 3 * w);
-    L.ob_dir_stride = obcap + group;   // padding slots take the codes of stayers
+    if (obcap > MAX_SLOTS) return fail(PIC_E_ARG, "outbox capacity too large (at most 2^28 slots)");
+    L.ob_dir_stride = obcap;
     L.off_ob_dir = take(tiles * ns * L.ob_dir_stride * 4);
     L.off_ob_cnt = take(tiles * ns * 4);
     L.off_ob_boff = take(tiles * ns * (pic::ncodes<3>() + 1) * 4);

@@ -50,7 +50,7 @@ struct Params {
     int32_t *ob_dir;          // [tile*species][ob_dir_stride]
     int32_t *ob_cnt;          // [tile*species]
     int64_t ob_cap;
-    int64_t ob_dir_stride;    // ob_cap plus padding slots
+    int64_t ob_dir_stride;    // slots per outbox direction list (ob_cap)
     R *tmp;                   // sort staging [(D+3)][cap_total]
     int32_t *err;             // latched error bits
     unsigned long long *nearface;
@@ -70,6 +70,25 @@ __device__ __forceinline__ int wrapi(int i, int n)
 {
     int r = i % n;
     return r < 0 ? r + n : r;
+}
+
+// Product of two small non-negative integers (LDS block indices and strides,
+// both far below 2^23): v_mul_i32_i24 issues at the full VALU rate, the
+// 32-bit v_mul_lo_u32 at a quarter of it.
+__device__ __forceinline__ int imul24(int a, int b) { return (int)__umul24((unsigned)a, (unsigned)b); }
+
+// Loads and stores at a 32-bit byte offset from a uniform base pointer: the
+// memory instruction adds the 64-bit scalar base and the 32-bit vector
+// offset itself, so a particle index costs one shift for every plane.
+template <typename T>
+__device__ __forceinline__ T ld_off(const T *base, uint32_t off)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off);
+}
+template <typename T>
+__device__ __forceinline__ void st_off(T *base, uint32_t off, T v)
+{
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off) = v;
 }
 
 template <int D>
@@ -216,14 +235,14 @@ __device__ __forceinline__ R interp_comp(const R *__restrict__ F, int s1, int s2
     if constexpr (D == 1) {
         return F[b] * (R(1) - w0) + F[b + 1] * w0;
     } else {
-        b += (h1 ? st.bh[1] : st.bn[1]) * s1;
+        b += imul24(h1 ? st.bh[1] : st.bn[1], s1);
         R w1 = h1 ? st.wh[1] : st.wn[1];
         if constexpr (D == 2) {
             R a0 = F[b] * (R(1) - w0) + F[b + 1] * w0;
             R a1 = F[b + s1] * (R(1) - w0) + F[b + s1 + 1] * w0;
             return a0 * (R(1) - w1) + a1 * w1;
         } else {
-            b += (h2 ? st.bh[2] : st.bn[2]) * s2;
+            b += imul24(h2 ? st.bh[2] : st.bn[2], s2);
             R w2 = h2 ? st.wh[2] : st.wn[2];
             R a00 = F[b] * (R(1) - w0) + F[b + 1] * w0;
             R a10 = F[b + s1] * (R(1) - w0) + F[b + s1 + 1] * w0;
@@ -514,11 +533,11 @@ __device__ __forceinline__ void zigzag(A *sJ, const CurBox<D> &cb, const int32_t
     segment_values<R, D>(F1, W1, d1, v1);
     segment_values<R, D>(F2, W2, d2, v2);
     const int s1 = cb.e0, s2 = cb.e0 * cb.e1;
-    const int b1 = l1[0] + (D > 1 ? l1[1] * s1 : 0) + (D > 2 ? l1[2] * s2 : 0);
+    const int b1 = l1[0] + (D > 1 ? imul24(l1[1], s1) : 0) + (D > 2 ? imul24(l1[2], s2) : 0);
 #pragma unroll
     for (int k = 0; k < NV; ++k) lds_add(sJ + b1 + seg_offset<D>(cb, k), same ? v1[k] + v2[k] : v1[k]);
     if (!same) {
-        const int b2 = l2[0] + (D > 1 ? l2[1] * s1 : 0) + (D > 2 ? l2[2] * s2 : 0);
+        const int b2 = l2[0] + (D > 1 ? imul24(l2[1], s1) : 0) + (D > 2 ? imul24(l2[2], s2) : 0);
 #pragma unroll
         for (int k = 0; k < NV; ++k) lds_add(sJ + b2 + seg_offset<D>(cb, k), v2[k]);
     }

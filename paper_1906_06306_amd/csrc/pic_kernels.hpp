@@ -208,14 +208,20 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int t, unsig
         const int cnt = p.seg_cnt[ts];
         const R q = p.charge[td.box * p.nspecies + s];
         const R sq = p.qm[td.box * p.nspecies + s];
-        // uniform per-species base pointers, 32-bit particle indices
-        R *X[3], *V[3], *XO[3];
+        // uniform per-species base pointers (segment and outbox planes);
+        // particle slots are 32-bit byte offsets from them (segment and
+        // outbox capacities are bounded so that they fit)
+        R *X[3], *V[3], *XO[3], *OX[3], *OU[3];
+        const int64_t ob = (int64_t)ts * p.ob_cap;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             X[d] = p.pos + (d < D ? d : 0) * cap + so;
             XO[d] = p.xold + (d < D ? d : 0) * cap + so;
             V[d] = p.u + d * cap + so;
+            OX[d] = p.ob_pos + ob * D + (d < D ? d : 0) * p.ob_cap;
+            OU[d] = p.ob_u + ob * 3 + d * p.ob_cap;
         }
+        int32_t *const OD = p.ob_dir + (int64_t)ts * p.ob_dir_stride;
         int keep = 0, nleave = 0;
         // next group's particles, loaded one group ahead.  Segment
         // capacities are multiples of the group size, so every lane of a
@@ -227,11 +233,11 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int t, unsig
 #pragma unroll
             for (int d = 0; d < 3; ++d) nx[j][d] = nu[j][d] = R(0);
             if (cnt > 0) {
-                const int i = j * (int)blockDim.x + (int)threadIdx.x;
+                const uint32_t o = (uint32_t)(j * (int)blockDim.x + (int)threadIdx.x) * (uint32_t)sizeof(R);
 #pragma unroll
-                for (int d = 0; d < D; ++d) nx[j][d] = X[d][i];
+                for (int d = 0; d < D; ++d) nx[j][d] = ld_off(X[d], o);
 #pragma unroll
-                for (int m = 0; m < 3; ++m) nu[j][m] = V[m][i];
+                for (int m = 0; m < 3; ++m) nu[j][m] = ld_off(V[m], o);
             }
         }
         for (int c0 = 0; c0 < cnt; c0 += G) {
@@ -252,11 +258,12 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int t, unsig
             if (c0 + G < cnt) {
 #pragma unroll
                 for (int j = 0; j < U; ++j) {
-                    const int i = c0 + G + j * (int)blockDim.x + (int)threadIdx.x;
+                    const uint32_t o =
+                        (uint32_t)(c0 + G + j * (int)blockDim.x + (int)threadIdx.x) * (uint32_t)sizeof(R);
 #pragma unroll
-                    for (int d = 0; d < D; ++d) nx[j][d] = X[d][i];
+                    for (int d = 0; d < D; ++d) nx[j][d] = ld_off(X[d], o);
 #pragma unroll
-                    for (int m = 0; m < 3; ++m) nu[j][m] = V[m][i];
+                    for (int m = 0; m < 3; ++m) nu[j][m] = ld_off(V[m], o);
                 }
             }
             int delta[U][3], code[U];
@@ -300,47 +307,34 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int t, unsig
                 for (int j = 0; j < U; ++j) stay[j] = valid[j] && code[j] == centre_code<D>();
                 const int tot = wg_scan_flags<U>(stay, sTot, parity, pre);
                 parity ^= 1;
-                const int64_t ob = (int64_t)ts * p.ob_cap;
 #pragma unroll
                 for (int j = 0; j < U; ++j) {
-                    // one store path for every lane: stayers to their compacted
-                    // slot, leavers to the outbox, lanes past the count back to
-                    // their own free slot; the destination planes are selected,
-                    // so the stores do not diverge
+                    // stayers to their compacted slot, leavers to the outbox
+                    // (the two store sets run under complementary lane masks;
+                    // lanes past the count store nothing)
                     const int lane_idx = j * (int)blockDim.x + (int)threadIdx.x;
-                    int64_t slot = nleave + (lane_idx - pre[j]);
-                    const bool leave = valid[j] && !stay[j];
-                    if (leave && slot >= p.ob_cap) {
-                        errs |= ERR_CAPACITY;     // state is invalid from here on
-                        slot = p.ob_cap - 1;
-                    }
-                    R *dx[3], *du[3];
-                    int64_t k;
-                    if (leave) {
-                        k = slot;
+                    const int32_t origin = (int32_t)(so + c0 + lane_idx);   // slot read from
+                    if (stay[j]) {
+                        const uint32_t k = (uint32_t)(keep + pre[j]);
+                        const uint32_t o = k * (uint32_t)sizeof(R);
 #pragma unroll
-                        for (int d = 0; d < 3; ++d) {
-                            dx[d] = p.ob_pos + ob * D + (d < D ? d : 0) * p.ob_cap;
-                            du[d] = p.ob_u + ob * 3 + d * p.ob_cap;
+                        for (int d = 0; d < D; ++d) st_off(X[d], o, x2[j][d]);
+#pragma unroll
+                        for (int m = 0; m < 3; ++m) st_off(V[m], o, u[j][m]);
+                        if (p.ids) st_off(p.ids + so, k * 4u, origin);
+                    } else if (valid[j]) {
+                        int64_t slot = nleave + (lane_idx - pre[j]);
+                        if (slot >= p.ob_cap) {
+                            errs |= ERR_CAPACITY;     // state is invalid from here on
+                            slot = p.ob_cap - 1;
                         }
-                    } else {
-                        k = stay[j] ? keep + pre[j] : c0 + lane_idx;
+                        const uint32_t o = (uint32_t)slot * (uint32_t)sizeof(R);
 #pragma unroll
-                        for (int d = 0; d < 3; ++d) {
-                            dx[d] = X[d];
-                            du[d] = V[d];
-                        }
-                    }
+                        for (int d = 0; d < D; ++d) st_off(OX[d], o, x2[j][d] - R(delta[j][d] * T[d]));
 #pragma unroll
-                    for (int d = 0; d < D; ++d) dx[d][k] = x2[j][d] - R(delta[j][d] * T[d]);
-#pragma unroll
-                    for (int m = 0; m < 3; ++m) du[m][k] = u[j][m];
-                    p.ob_dir[(int64_t)ts * p.ob_dir_stride + (leave ? slot : p.ob_cap + lane_idx)] = code[j];
-                    if (p.ids) {
-                        // origin tracking: global slot this particle was read from
-                        const int32_t origin = (int32_t)(so + c0 + lane_idx);
-                        if (leave) p.ob_ids[ob + slot] = origin;
-                        else p.ids[so + k] = origin;
+                        for (int m = 0; m < 3; ++m) st_off(OU[m], o, u[j][m]);
+                        st_off(OD, (uint32_t)slot * 4u, code[j]);
+                        if (p.ids) st_off(p.ob_ids + ob, (uint32_t)slot * 4u, origin);
                     }
                 }
                 const int nvalid = min(G, cnt - c0);
