@@ -63,6 +63,7 @@ struct Layout {
     uint64_t off_ob_ids, off_adj_lj, off_adj_eblk, off_adj_bblk, off_ob_boff, off_ob_idx, off_jtmp, off_rho_prev;
     int64_t fblk_cells, n_input;
     int64_t jblk_cells, rblk_cells, max_count, max_ntb, nchunks_max, ob_dir_stride;
+    int32_t order_shift;   // segment counts are bucketed by count >> order_shift for the dispatch order
     std::vector<TileDesc> tiles;
     std::vector<int64_t> seg_off;
     std::vector<int32_t> seg_cap;
@@ -160,7 +161,6 @@ pic_status make_layout(const pic_config *c, const int64_t *counts, Layout &L)
     L.seg_off.assign(tiles * ns, 0);
     L.seg_cap.assign(tiles * ns, 0);
     int64_t cap_total = 0, max_cap = 0;
-    std::vector<int64_t> load(tiles, 0);
     for (int64_t t = 0; t < tiles; ++t) {
         const int b = L.tiles[t].box;
         const int64_t ntb = (int64_t)L.tiles[t].nt[0] * L.tiles[t].nt[1] * L.tiles[t].nt[2];
@@ -178,14 +178,16 @@ pic_status make_layout(const pic_config *c, const int64_t *counts, Layout &L)
             L.seg_cap[t * ns + s] = (int32_t)cap;
             cap_total += cap;
             max_cap = std::max(max_cap, cap);
-            load[t] += cap;
         }
     }
-    // tile visiting order: heaviest first (stable), so that the largest
-    // tiles are dispatched first and the tail is made of small ones
-    L.order.resize(tiles);
-    for (int64_t t = 0; t < tiles; ++t) L.order[t] = (int32_t)t;
-    std::stable_sort(L.order.begin(), L.order.end(), [&](int32_t a, int32_t b) { return load[a] > load[b]; });
+    // segment visiting order before the first push (largest capacity first);
+    // every push launch re-sorts the segments by their current counts
+    L.order.resize(tiles * ns);
+    for (int64_t w = 0; w < tiles * ns; ++w) L.order[w] = (int32_t)w;
+    std::stable_sort(L.order.begin(), L.order.end(),
+                     [&](int32_t a, int32_t b) { return L.seg_cap[a] > L.seg_cap[b]; });
+    L.order_shift = 0;
+    while ((max_cap >> L.order_shift) >= pic::ORDER_BUCKETS) ++L.order_shift;
     const int64_t obcap = c->outbox_capacity > 0 ? round_up(c->outbox_capacity, 64)
                                                  : round_up(std::max<int64_t>(256, max_cap / 4), 64);
     int64_t cb = 1, rb = 1;
@@ -226,7 +228,7 @@ pic_status make_layout(const pic_config *c, const int64_t *counts, Layout &L)
     P.off_flags = take(8);
     P.off_ids = take(track ? cap_total * 4 : 0);
     L.off_tmp = take((D + 3) * cap_total * w);
-    L.off_jblk = take(tiles * 3 * cb * w);
+    L.off_jblk = take(tiles * ns * 3 * cb * w);
     L.off_rblk = take(tiles * rb * 8);
     L.off_part = take(tiles * pic::NPART * 8);
     L.off_ob_pos = take(tiles * ns * obcap * D * w);
@@ -243,7 +245,7 @@ pic_status make_layout(const pic_config *c, const int64_t *counts, Layout &L)
     L.off_charge = take(nb * ns * w);
     L.off_qm = take(nb * ns * w);
     L.off_mass = take(nb * ns * 8);
-    L.off_order = take(tiles * 4);
+    L.off_order = take(tiles * ns * 4);
     L.off_queue = take(4);
     L.off_key = take(L.max_count * 4);
     L.off_xl = take(D * L.max_count * w);
@@ -326,7 +328,7 @@ Params<R> params(pic_ctx *x)
     p.err = reinterpret_cast<int32_t *>(ws + L.pub.off_error);
     p.nearface = reinterpret_cast<unsigned long long *>(ws + L.pub.off_flags);
     p.queue = reinterpret_cast<int32_t *>(ws + L.off_queue);
-    p.order = reinterpret_cast<const int32_t *>(ws + L.off_order);
+    p.order = reinterpret_cast<int32_t *>(ws + L.off_order);
     if (x->track) {
         p.ids = reinterpret_cast<int32_t *>(ws + L.pub.off_ids);
         p.ob_ids = reinterpret_cast<int32_t *>(ws + L.off_ob_ids);
@@ -390,12 +392,24 @@ struct Impl {
         return x->order == 4 ? fdtd_order<4>(x, phase) : fdtd_order<2>(x, phase);
     }
 
+    // segments by decreasing count into p.order (one work-group)
+    static pic_status order_segments(pic_ctx *x, const Params<R> &p)
+    {
+        hipLaunchKernelGGL(pic::k_order, dim3(1), dim3(pic::ORDER_BUCKETS), 0, x->stream, p.seg_cnt,
+                           (int32_t)(x->L.pub.tiles_total * x->ns), x->L.order_shift, p.order);
+        HIP_OK(hipGetLastError());
+        return PIC_OK;
+    }
+
     template <bool FUSED, bool HALFB, typename A, int TC, bool WALLS, int PUSHER>
     static pic_status push_launch(pic_ctx *x)
     {
         Params<R> p = params<R>(x);
         size_t lds = push_lds(x, FUSED, sizeof(A));
         dim3 b(x->block);
+        const int64_t items = x->L.pub.tiles_total * x->ns;
+        pic_status st0 = order_segments(x, p);
+        if (st0) return st0;
         if (x->persistent) {
             auto kern = pic::k_push_persistent<R, D, FUSED, HALFB, A, PUSH_UNROLL, TC, WALLS, PUSHER>;
             pic_status st = set_lds(kern, lds);
@@ -403,7 +417,7 @@ struct Impl {
             int per_cu = 0;
             HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kern),
                                                                 x->block, lds));
-            const int64_t grid = std::min<int64_t>(x->L.pub.tiles_total, (int64_t)std::max(per_cu, 1) * x->n_cu);
+            const int64_t grid = std::min<int64_t>(items, (int64_t)std::max(per_cu, 1) * x->n_cu);
             st = fill<int32_t>(x, p.queue, 1, 0);
             if (st) return st;
             hipLaunchKernelGGL(kern, dim3((unsigned)grid), b, lds, x->stream, p);
@@ -411,7 +425,7 @@ struct Impl {
             auto kern = pic::k_push<R, D, FUSED, HALFB, A, PUSH_UNROLL, TC, WALLS, PUSHER>;
             pic_status st = set_lds(kern, lds);
             if (st) return st;
-            hipLaunchKernelGGL(kern, dim3((unsigned)x->L.pub.tiles_total), b, lds, x->stream, p);
+            hipLaunchKernelGGL(kern, dim3((unsigned)items), b, lds, x->stream, p);
         }
         HIP_OK(hipGetLastError());
         return PIC_OK;
@@ -455,16 +469,17 @@ struct Impl {
         Params<R> p = params<R>(x);
         dim3 g((unsigned)x->L.pub.tiles_total);
         if (unfused_part) {
+            const dim3 gs((unsigned)(x->L.pub.tiles_total * x->ns));   // one work-group per segment
             if (x->acc_working) {
                 size_t lds = 3 * x->L.jblk_cells * sizeof(R);
                 pic_status st = set_lds(pic::k_deposit<R, D, R>, lds);
                 if (st) return st;
-                hipLaunchKernelGGL((pic::k_deposit<R, D, R>), g, dim3(x->block), lds, x->stream, p);
+                hipLaunchKernelGGL((pic::k_deposit<R, D, R>), gs, dim3(x->block), lds, x->stream, p);
             } else {
                 size_t lds = 3 * x->L.jblk_cells * sizeof(double);
                 pic_status st = set_lds(pic::k_deposit<R, D, double>, lds);
                 if (st) return st;
-                hipLaunchKernelGGL((pic::k_deposit<R, D, double>), g, dim3(x->block), lds, x->stream, p);
+                hipLaunchKernelGGL((pic::k_deposit<R, D, double>), gs, dim3(x->block), lds, x->stream, p);
             }
             HIP_OK(hipGetLastError());
         }
@@ -555,7 +570,7 @@ struct Impl {
         if (!st) st = fill<R>(x, p.J, 3 * L.pub.cells_total, R(0));
         if (!st) st = fill<R>(x, p.E, 3 * L.pub.cells_total, R(0));
         if (!st) st = fill<R>(x, p.B, 3 * L.pub.cells_total, R(0));
-        if (!st) st = fill<R>(x, p.jblk, L.pub.tiles_total * 3 * L.jblk_cells, R(0));
+        if (!st) st = fill<R>(x, p.jblk, L.pub.tiles_total * x->ns * 3 * L.jblk_cells, R(0));
         if (st) return st;
         int64_t id_base = 0;
         for (int b = 0; b < x->nb; ++b) {

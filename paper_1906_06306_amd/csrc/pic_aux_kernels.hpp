@@ -32,6 +32,54 @@ __global__ void k_load_field(R *dst, int64_t cells_total, int64_t cell0, const d
     }
 }
 
+// ------------------------------------------------------- dispatch order
+
+// Visiting order of the (tile, species) segments for the push and deposit
+// launches: decreasing particle count, so that the largest segments start
+// first and the end of a launch is made of small ones (densities become
+// very uneven as a plasma compresses).  Counting sort over the key
+// count >> shift in one work-group of ORDER_BUCKETS threads; segments with
+// equal keys come in no particular order, which the results do not depend
+// on (every segment writes its own current block and counters).
+constexpr int ORDER_BUCKETS = 1024;
+
+__global__ void __launch_bounds__(ORDER_BUCKETS) k_order(const int32_t *cnt, int32_t n, int32_t shift, int32_t *order)
+{
+    __shared__ int hist[ORDER_BUCKETS];
+    __shared__ int wsum[ORDER_BUCKETS / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    hist[tid] = 0;
+    __syncthreads();
+    for (int w = tid; w < n; w += ORDER_BUCKETS)
+        atomicAdd(&hist[ORDER_BUCKETS - 1 - min(cnt[w] >> shift, ORDER_BUCKETS - 1)], 1);
+    __syncthreads();
+    // exclusive prefix over the buckets: wave scans, then the wave totals
+    const int v = hist[tid];
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    if (tid == 0) {
+        int run = 0;
+        for (int k = 0; k < ORDER_BUCKETS / 64; ++k) {
+            const int t = wsum[k];
+            wsum[k] = run;
+            run += t;
+        }
+    }
+    __syncthreads();
+    hist[tid] = x - v + wsum[wv];
+    __syncthreads();
+    for (int w = tid; w < n; w += ORDER_BUCKETS) {
+        const int pos = atomicAdd(&hist[ORDER_BUCKETS - 1 - min(cnt[w] >> shift, ORDER_BUCKETS - 1)], 1);
+        order[pos] = w;
+    }
+}
+
 // -------------------------------------------------------------- binning
 
 struct BinGeom {

@@ -45,7 +45,7 @@ struct Params {
     const int64_t *seg_off;   // [tile][species]
     const int32_t *seg_cap;
     int32_t *seg_cnt;
-    R *jblk;                  // [tile][3][JV]
+    R *jblk;                  // [tile*species][3][JV]
     R *ob_pos, *ob_u;         // [tile*species][D|3][ob_cap]
     int32_t *ob_dir;          // [tile*species][ob_dir_stride]
     int32_t *ob_cnt;          // [tile*species]
@@ -55,7 +55,7 @@ struct Params {
     int32_t *err;             // latched error bits
     unsigned long long *nearface;
     int32_t *queue;           // work counter of the persistent walker
-    const int32_t *order;     // tile visiting order of the persistent walker
+    int32_t *order;           // (tile, species) segments in visiting order
     int32_t *ids;             // [cap_total] origin of each particle, or null
     int32_t *ob_ids;          // [tile*species][ob_cap] origin of each leaver
     int32_t *ob_boff;         // [tile*species][ncodes+1] outbox bucket starts by direction code

@@ -160,8 +160,10 @@ __device__ __forceinline__ void compact_chunk(const Params<R> &p, int ts, int64_
 // coalesced while U loads per array are in flight; the stable compaction
 // runs once per group.
 template <typename R, int D, bool FUSED, bool HALFB, typename A, int U, int TC, bool WALLS, int PUSHER>
-__device__ __forceinline__ void push_tile(const Params<R> &p, const int t, unsigned char *smem)
+__device__ __forceinline__ void push_tile(const Params<R> &p, const int w, unsigned char *smem)
 {
+    // work item w = one (tile, species) segment
+    const int t = w / p.nspecies, s = w - t * p.nspecies;
     const TileDesc td = p.tiles[t];
     // tile edge: a compile-time constant when TC > 0 (strides, LDS offsets
     // and the halves T/2 then fold into the instructions), else the runtime one
@@ -202,8 +204,8 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int t, unsig
     const int G = U * blockDim.x;
     int parity = 0;
     int32_t errs = 0;
-    for (int s = 0; s < p.nspecies; ++s) {
-        const int ts = t * p.nspecies + s;
+    {
+        const int ts = w;
         const int64_t so = p.seg_off[ts];
         const int cnt = p.seg_cnt[ts];
         const R q = p.charge[td.box * p.nspecies + s];
@@ -364,12 +366,13 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int t, unsig
     latch_wave(p.err, errs);
     if constexpr (FUSED) {
         __syncthreads();
-        R *blk = p.jblk + (int64_t)t * 3 * cb.n;
+        R *blk = p.jblk + (int64_t)w * 3 * cb.n;
         for (int k = threadIdx.x; k < 3 * cb.n; k += blockDim.x) blk[k] = (R)sJ[k];
     }
 }
 
-// One work-group per tile, tiles dispatched heaviest first.
+// One work-group per (tile, species) segment, segments dispatched in the
+// order k_order wrote (largest particle count first).
 template <typename R, int D, bool FUSED, bool HALFB, typename A, int U, int TC, bool WALLS, int PUSHER>
 __global__ void __launch_bounds__(1024) k_push(Params<R> p)
 {
@@ -377,9 +380,9 @@ __global__ void __launch_bounds__(1024) k_push(Params<R> p)
     push_tile<R, D, FUSED, HALFB, A, U, TC, WALLS, PUSHER>(p, p.order[blockIdx.x], smem);
 }
 
-// Persistent tile walker: a grid sized to the resident work-groups pulls
-// tiles (heaviest first) from an atomic counter until every tile is taken;
-// every work-group leaves the loop when the counter passes the tile count.
+// Persistent walker: a grid sized to the resident work-groups pulls
+// segments (largest first) from an atomic counter until every one is taken;
+// every work-group leaves the loop when the counter passes the segment count.
 template <typename R, int D, bool FUSED, bool HALFB, typename A, int U, int TC, bool WALLS, int PUSHER>
 __global__ void __launch_bounds__(1024) k_push_persistent(Params<R> p)
 {
@@ -390,7 +393,7 @@ __global__ void __launch_bounds__(1024) k_push_persistent(Params<R> p)
         __syncthreads();
         const int k = next;
         __syncthreads();
-        if (k >= p.ntiles) break;
+        if (k >= p.ntiles * p.nspecies) break;
         push_tile<R, D, FUSED, HALFB, A, U, TC, WALLS, PUSHER>(p, p.order[k], smem);
         __syncthreads();
     }
@@ -402,15 +405,16 @@ template <typename R, int D, typename A>
 __global__ void __launch_bounds__(1024) k_deposit(Params<R> p)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int t = p.order ? p.order[blockIdx.x] : (int)blockIdx.x;
+    const int w = p.order[blockIdx.x];              // (tile, species) segment
+    const int t = w / p.nspecies, s = w - t * p.nspecies;
     const TileDesc td = p.tiles[t];
     const CurBox<D> cb(p.T);
     A *sJ = reinterpret_cast<A *>(smem);
     for (int k = threadIdx.x; k < 3 * cb.n; k += blockDim.x) sJ[k] = A(0);
     __syncthreads();
     const int64_t cap = p.cap_total;
-    for (int s = 0; s < p.nspecies; ++s) {
-        const int ts = t * p.nspecies + s;
+    {
+        const int ts = w;
         const int64_t so = p.seg_off[ts];
         const int cnt = p.seg_cnt[ts];
         const R q = p.charge[td.box * p.nspecies + s];
@@ -429,12 +433,13 @@ __global__ void __launch_bounds__(1024) k_deposit(Params<R> p)
         }
     }
     __syncthreads();
-    R *blk = p.jblk + (int64_t)t * 3 * cb.n;
+    R *blk = p.jblk + (int64_t)w * 3 * cb.n;
     for (int k = threadIdx.x; k < 3 * cb.n; k += blockDim.x) blk[k] = (R)sJ[k];
 }
 
-// cur_exchange: J on the lattice = sum of the current blocks of the tile
-// and of its neighbours whose halo covers the cell (fixed order).
+// cur_exchange: J on the lattice = sum of the current blocks (one per
+// species) of the tile and of its neighbours whose halo covers the cell
+// (fixed order: neighbour, then species).
 template <typename R, int D>
 __global__ void __launch_bounds__(256) k_fold(Params<R> p)
 {
@@ -462,11 +467,13 @@ __global__ void __launch_bounds__(256) k_fold(Params<R> p)
                     }
                     if (!in) continue;
                     const int nid = td.tile0 + nc[0] + td.nt[0] * (nc[1] + td.nt[1] * nc[2]);
-                    const R *blk = p.jblk + (int64_t)nid * 3 * cb.n;
                     const int idx = bi[0] + cb.e0 * (bi[1] + cb.e1 * bi[2]);
-                    acc[0] += blk[idx];
-                    acc[1] += blk[cb.n + idx];
-                    acc[2] += blk[2 * cb.n + idx];
+                    for (int sp = 0; sp < p.nspecies; ++sp) {
+                        const R *blk = p.jblk + ((int64_t)nid * p.nspecies + sp) * 3 * cb.n;
+                        acc[0] += blk[idx];
+                        acc[1] += blk[cb.n + idx];
+                        acc[2] += blk[2 * cb.n + idx];
+                    }
                 }
         const int gx = td.tc[0] * T0 + l[0];
         const int gy = D > 1 ? td.tc[1] * T1 + l[1] : 0;
