@@ -462,10 +462,15 @@ __global__ void __launch_bounds__(256) k_fold(Params<R> p)
                         if (d < D) {
                             bi[d] = l[d] - o[d] * p.T[d] + 1;
                             in = in && bi[d] >= 0 && bi[d] < p.T[d] + 3;
-                            nc[d] = wrapi(td.tc[d] + o[d], td.nt[d]);
                         }
                     }
                     if (!in) continue;
+#pragma unroll
+                    for (int d = 0; d < D; ++d) {
+                        // neighbour tile coordinate, periodic (one step at most)
+                        const int v = td.tc[d] + o[d];
+                        nc[d] = v < 0 ? v + td.nt[d] : (v >= td.nt[d] ? v - td.nt[d] : v);
+                    }
                     const int nid = td.tile0 + nc[0] + td.nt[0] * (nc[1] + td.nt[1] * nc[2]);
                     const int idx = bi[0] + cb.e0 * (bi[1] + cb.e1 * bi[2]);
                     for (int sp = 0; sp < p.nspecies; ++sp) {
