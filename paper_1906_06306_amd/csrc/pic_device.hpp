@@ -72,6 +72,18 @@ __device__ __forceinline__ int wrapi(int i, int n)
     return r < 0 ? r + n : r;
 }
 
+// Tile of this work-group in launches with one work-group per tile.  The
+// dispatcher hands consecutive work-groups to the eight dies (XCDs, each
+// with its own L2) in turn; this bijection gives every die a contiguous
+// range of tiles instead, so that neighbouring tiles, which share cache
+// lines of the field planes and each other's halos, meet in one L2.
+__device__ __forceinline__ int xcd_tile(int b, int n)
+{
+    constexpr int NXCD = 8;
+    const int x = b % NXCD, l = b / NXCD, per = n / NXCD, rem = n % NXCD;
+    return x < rem ? x * (per + 1) + l : rem * (per + 1) + (x - rem) * per + l;
+}
+
 // Product of two small non-negative integers (LDS block indices and strides,
 // both far below 2^23): v_mul_i32_i24 issues at the full VALU rate, the
 // 32-bit v_mul_lo_u32 at a quarter of it.

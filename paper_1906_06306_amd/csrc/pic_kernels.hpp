@@ -438,48 +438,99 @@ __global__ void __launch_bounds__(1024) k_deposit(Params<R> p)
 }
 
 // cur_exchange: J on the lattice = sum of the current blocks (one per
-// species) of the tile and of its neighbours whose halo covers the cell
-// (fixed order: neighbour, then species).
+// species) of the tile and of its neighbours whose halo covers the cell, in
+// a fixed order (species, then neighbour offsets ascending, z major).  A
+// block covers local cells -1..T+1, so along each dimension a cell is
+// covered by its own tile and, for l < 2, the tile below or, for l = T-1,
+// the tile above (edges T >= 4); the up to 2^D loads of a species are
+// issued together, without branches.  Edges of 2 take the general loop.
 template <typename R, int D>
 __global__ void __launch_bounds__(256) k_fold(Params<R> p)
 {
-    const int t = blockIdx.x;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
     const TileDesc td = p.tiles[t];
     const CurBox<D> cb(p.T);
     const int T0 = p.T[0], T1 = D > 1 ? p.T[1] : 1, T2 = D > 2 ? p.T[2] : 1;
     const int ncell = T0 * T1 * T2;
+    bool small = false;
+#pragma unroll
+    for (int d = 0; d < D; ++d) small = small || p.T[d] < 4;
     for (int k = threadIdx.x; k < ncell; k += blockDim.x) {
         const int l[3] = {k % T0, (k / T0) % T1, k / (T0 * T1)};
         R acc[3] = {0, 0, 0};
-        for (int oz = (D > 2 ? -1 : 0); oz <= (D > 2 ? 1 : 0); ++oz)
-            for (int oy = (D > 1 ? -1 : 0); oy <= (D > 1 ? 1 : 0); ++oy)
-                for (int ox = -1; ox <= 1; ++ox) {
-                    const int o[3] = {ox, oy, oz};
-                    int bi[3] = {0, 0, 0}, nc[3] = {0, 0, 0};
-                    bool in = true;
+        if (!small) {
+            // per dimension: offsets o0 < o1 and whether o1 covers the cell
+            int o0[3] = {0, 0, 0}, o1[3] = {0, 0, 0};
+            bool v1[3] = {false, false, false};
 #pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        if (d < D) {
-                            bi[d] = l[d] - o[d] * p.T[d] + 1;
-                            in = in && bi[d] >= 0 && bi[d] < p.T[d] + 3;
-                        }
-                    }
-                    if (!in) continue;
+            for (int d = 0; d < D; ++d) {
+                const bool low = l[d] < 2;
+                o0[d] = low ? -1 : 0;
+                o1[d] = low ? 0 : 1;
+                v1[d] = low || l[d] >= p.T[d] - 1;
+            }
+            constexpr int NCOMB = 1 << D;
+            int idx[NCOMB];
+            int64_t base[NCOMB];
+            bool ok[NCOMB];
 #pragma unroll
-                    for (int d = 0; d < D; ++d) {
-                        // neighbour tile coordinate, periodic (one step at most)
-                        const int v = td.tc[d] + o[d];
-                        nc[d] = v < 0 ? v + td.nt[d] : (v >= td.nt[d] ? v - td.nt[d] : v);
-                    }
-                    const int nid = td.tile0 + nc[0] + td.nt[0] * (nc[1] + td.nt[1] * nc[2]);
-                    const int idx = bi[0] + cb.e0 * (bi[1] + cb.e1 * bi[2]);
-                    for (int sp = 0; sp < p.nspecies; ++sp) {
-                        const R *blk = p.jblk + ((int64_t)nid * p.nspecies + sp) * 3 * cb.n;
-                        acc[0] += blk[idx];
-                        acc[1] += blk[cb.n + idx];
-                        acc[2] += blk[2 * cb.n + idx];
-                    }
+            for (int cmb = 0; cmb < NCOMB; ++cmb) {
+                int bi[3] = {0, 0, 0}, nc[3] = {0, 0, 0};
+                bool valid = true;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    const bool hi = (cmb >> d) & 1;
+                    const int o = hi ? o1[d] : o0[d];
+                    valid = valid && (!hi || v1[d]);
+                    bi[d] = l[d] - o * p.T[d] + 1;
+                    const int v = td.tc[d] + o;    // neighbour tile, periodic
+                    nc[d] = v < 0 ? v + td.nt[d] : (v >= td.nt[d] ? v - td.nt[d] : v);
                 }
+                ok[cmb] = valid;
+                // an uncovered combination reads the tile's own entry and adds 0
+                const int nid = valid ? td.tile0 + nc[0] + td.nt[0] * (nc[1] + td.nt[1] * nc[2]) : t;
+                idx[cmb] = valid ? bi[0] + cb.e0 * (bi[1] + cb.e1 * bi[2])
+                                 : l[0] + 1 + cb.e0 * ((D > 1 ? l[1] + 1 : 0) + cb.e1 * (D > 2 ? l[2] + 1 : 0));
+                base[cmb] = (int64_t)nid * p.nspecies;
+            }
+            for (int sp = 0; sp < p.nspecies; ++sp) {
+                R v[NCOMB][3];
+#pragma unroll
+                for (int cmb = 0; cmb < NCOMB; ++cmb) {
+                    const R *blk = p.jblk + (base[cmb] + sp) * 3 * cb.n + idx[cmb];
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) v[cmb][m] = blk[m * cb.n];
+                }
+#pragma unroll
+                for (int cmb = 0; cmb < NCOMB; ++cmb) {
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) acc[m] += ok[cmb] ? v[cmb][m] : R(0);
+                }
+            }
+        } else {
+            for (int sp = 0; sp < p.nspecies; ++sp)
+                for (int oz = (D > 2 ? -1 : 0); oz <= (D > 2 ? 1 : 0); ++oz)
+                    for (int oy = (D > 1 ? -1 : 0); oy <= (D > 1 ? 1 : 0); ++oy)
+                        for (int ox = -1; ox <= 1; ++ox) {
+                            const int o[3] = {ox, oy, oz};
+                            int bi[3] = {0, 0, 0}, nc[3] = {0, 0, 0};
+                            bool in = true;
+#pragma unroll
+                            for (int d = 0; d < D; ++d) {
+                                bi[d] = l[d] - o[d] * p.T[d] + 1;
+                                in = in && bi[d] >= 0 && bi[d] < p.T[d] + 3;
+                                const int v = td.tc[d] + o[d];
+                                nc[d] = v < 0 ? v + td.nt[d] : (v >= td.nt[d] ? v - td.nt[d] : v);
+                            }
+                            if (!in) continue;
+                            const int nid = td.tile0 + nc[0] + td.nt[0] * (nc[1] + td.nt[1] * nc[2]);
+                            const int idx = bi[0] + cb.e0 * (bi[1] + cb.e1 * bi[2]);
+                            const R *blk = p.jblk + ((int64_t)nid * p.nspecies + sp) * 3 * cb.n;
+                            acc[0] += blk[idx];
+                            acc[1] += blk[cb.n + idx];
+                            acc[2] += blk[2 * cb.n + idx];
+                        }
+        }
         const int gx = td.tc[0] * T0 + l[0];
         const int gy = D > 1 ? td.tc[1] * T1 + l[1] : 0;
         const int gz = D > 2 ? td.tc[2] * T2 + l[2] : 0;
@@ -501,7 +552,7 @@ __global__ void __launch_bounds__(256) k_fold(Params<R> p)
 template <typename R, int D, int PHASE, int ORDER = 2>
 __global__ void __launch_bounds__(256) k_field(Params<R> p, R h)
 {
-    const int t = blockIdx.x;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
     const TileDesc td = p.tiles[t];
     const int T0 = p.T[0], T1 = D > 1 ? p.T[1] : 1, T2 = D > 2 ? p.T[2] : 1;
     const int ncell = T0 * T1 * T2;
@@ -611,7 +662,7 @@ __global__ void __launch_bounds__(256) k_field(Params<R> p, R h)
 template <typename R, int D>
 __global__ void __launch_bounds__(256) k_filter(Params<R> p, const R *__restrict__ src, R *__restrict__ dst)
 {
-    const int t = blockIdx.x;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
     const TileDesc td = p.tiles[t];
     const int T0 = p.T[0], T1 = D > 1 ? p.T[1] : 1, T2 = D > 2 ? p.T[2] : 1;
     const int ncell = T0 * T1 * T2;
@@ -647,7 +698,7 @@ template <typename R, int D>
 __global__ void __launch_bounds__(1024) k_migrate_out(Params<R> p)
 {
     __shared__ int sTot[2 * MAX_WAVES];
-    const int t = blockIdx.x;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t cap = p.cap_total;
     int parity = 0;
     for (int s = 0; s < p.nspecies; ++s) {
@@ -689,7 +740,7 @@ __global__ void __launch_bounds__(1024) k_migrate_bucket(Params<R> p)
     constexpr int NC = ncodes<D>();
     __shared__ int sCnt[MAX_WAVES * NC];
     __shared__ int sBase[NC + 1];
-    const int t = blockIdx.x;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int s = 0; s < p.nspecies; ++s) {
         const int ts = t * p.nspecies + s;
@@ -750,7 +801,7 @@ __global__ void __launch_bounds__(1024) k_migrate_in(Params<R> p)
     __shared__ int sOff[NC + 1];
     __shared__ int sSrc[NC];
     __shared__ int sB0[NC];
-    const int t = blockIdx.x;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
     const TileDesc td = p.tiles[t];
     const int64_t cap = p.cap_total;
     for (int s = 0; s < p.nspecies; ++s) {
@@ -814,7 +865,7 @@ template <typename R, int D>
 __global__ void __launch_bounds__(256) k_cell_sort(Params<R> p)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int t = blockIdx.x;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int T0 = p.T[0], T1 = D > 1 ? p.T[1] : 1, T2 = D > 2 ? p.T[2] : 1;
     const int ncell = T0 * T1 * T2;
