@@ -497,8 +497,11 @@ struct Impl {
             HIP_OK(hipGetLastError());
         }
         if (need_in) {
-            hipLaunchKernelGGL((pic::k_migrate_bucket<R, D>), g, dim3(256), 0, x->stream, p);
-            hipLaunchKernelGGL((pic::k_migrate_in<R, D>), g, dim3(x->block), 0, x->stream, p);
+            // one small work-group per (tile, species) segment: both kernels
+            // are chains of dependent loads, so many resident groups pay
+            const dim3 gs((unsigned)(x->L.pub.tiles_total * x->ns));
+            hipLaunchKernelGGL((pic::k_migrate_bucket<R, D>), gs, dim3(128), 0, x->stream, p);
+            hipLaunchKernelGGL((pic::k_migrate_in<R, D>), gs, dim3(128), 0, x->stream, p);
             HIP_OK(hipGetLastError());
         }
         if (sort) {

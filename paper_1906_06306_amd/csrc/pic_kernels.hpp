@@ -740,10 +740,10 @@ __global__ void __launch_bounds__(1024) k_migrate_bucket(Params<R> p)
     constexpr int NC = ncodes<D>();
     __shared__ int sCnt[MAX_WAVES * NC];
     __shared__ int sBase[NC + 1];
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    // one work-group per (tile, species) segment
+    const int ts = xcd_tile(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int s = 0; s < p.nspecies; ++s) {
-        const int ts = t * p.nspecies + s;
+    {
         const int n = (int)min((int64_t)p.ob_cnt[ts], p.ob_cap);
         const int32_t *dir = p.ob_dir + (int64_t)ts * p.ob_dir_stride;
         int32_t *boff = p.ob_boff + (int64_t)ts * (NC + 1);
@@ -801,11 +801,12 @@ __global__ void __launch_bounds__(1024) k_migrate_in(Params<R> p)
     __shared__ int sOff[NC + 1];
     __shared__ int sSrc[NC];
     __shared__ int sB0[NC];
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    // one work-group per (tile, species) segment
+    const int ts = xcd_tile(blockIdx.x, gridDim.x);
+    const int t = ts / p.nspecies, s = ts - t * p.nspecies;
     const TileDesc td = p.tiles[t];
     const int64_t cap = p.cap_total;
-    for (int s = 0; s < p.nspecies; ++s) {
-        const int ts = t * p.nspecies + s;
+    {
         const int64_t so = p.seg_off[ts];
         const int scap = p.seg_cap[ts];
         const int cnt = p.seg_cnt[ts];
@@ -852,7 +853,6 @@ __global__ void __launch_bounds__(1024) k_migrate_in(Params<R> p)
         }
         if (errs) latch(p.err, errs);
         if (threadIdx.x == 0) p.seg_cnt[ts] = min(cnt + total, scap);
-        __syncthreads();   // sOff / sSrc are rewritten for the next species
     }
 }
 
