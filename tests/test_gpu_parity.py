@@ -166,6 +166,42 @@ def test_fused_step_matches_oracle_and_unfused(D, n, T, ppc, prec, half_b_in_pus
     ref.close()
 
 
+@pytest.mark.parametrize("persistent", [False, True])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_uneven_segments_match_oracle(prec, persistent):
+    """Segments of very different counts (the push visits them largest first,
+    one work-group per (tile, species) segment, each with its own current
+    block): three fused steps against the oracle, particle counts exact."""
+    from paper_1906_06306_amd import _lib as L
+    plasma = synth.small_random(2, (64, 48), 4, seed=77, field_amp=0.05)
+    rng = np.random.default_rng(78)
+    # 70% of the electrons into the 8x8 cells of one tile, 30% of the
+    # positrons into another; the rest stay uniform
+    for s, (frac, corner) in enumerate([(0.7, (16.0, 8.0)), (0.3, (40.0, 32.0))]):
+        x = plasma.species[s].x
+        k = rng.random(x.shape[1]) < frac
+        x[0, k] = corner[0] + rng.random(int(k.sum())) * 8.0
+        x[1, k] = corner[1] + rng.random(int(k.sum())) * 8.0
+    T = (8, 8, 1)
+    sim = make_sim(plasma, T, prec, tile_capacity="auto", capacity_factor=1.5,
+                   options=L.PIC_OPT_PERSISTENT if persistent else 0)
+    _, _, _, off, cnt = sim.particle_views()
+    c = cnt.cpu().numpy()
+    assert c.max() > 20 * np.median(c)          # the uneven case is really uneven
+    tol = TOL[prec]
+    for step in range(3):
+        st = common_state(sim, plasma)          # each step from the GPU's own state
+        sim.step(1, fused=True, half_b_in_push=True)
+        st.step(1)
+        E, B, J = sim.fields_host(0)
+        assert rel(J, st.J) < tol and rel(E, st.E) < tol and rel(B, st.B) < tol, step
+    assert sim.error() == 0
+    _, _, _, off, cnt = sim.particle_views()
+    c = cnt.cpu().numpy()
+    assert [int(c[:, s].sum()) for s in range(2)] == [sp.x.shape[1] for sp in plasma.species]
+    sim.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_cell_sort_bit_exact(prec):
     D, n, T = 2, (64, 32, 1), (16, 8, 1)
