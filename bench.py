@@ -162,6 +162,10 @@ def run_gpu(plasma, args, precision, steps, warmup, tile, profile_only=False):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     push_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    sim.diagnostics()
+    # one more (untimed) step so that the diagnostics also state the
+    # discrete continuity residual of a step
+    step()
     diag = sim.diagnostics()
     sim.close()
     del sim
@@ -207,6 +211,25 @@ def pick_tile(plasma, args, precision):
     from paper_1906_06306_amd import autotune
     (T, _), res = autotune.tune(plasma, precision, blocks=(args.block,), capacity_factor=args.capacity, log=log)
     return T, {f"T{k[0]}_b{k[1]}": round(v * 1e3, 4) for k, v in res.items()}
+
+
+def copy_bandwidth():
+    """GB/s of a plain 1 GiB device-to-device copy (1 GiB read + 1 GiB
+    written), the best of 5: the streaming ceiling the push is set against."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    best = 0.0
+    for _ in range(6):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = max(best, 2 * a.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del a, b
+    torch.cuda.empty_cache()
+    return best
 
 
 def calibrate_copy():
@@ -513,6 +536,7 @@ def main():
     value = n_p * args.steps / r32["seconds"]
     pb = push_bytes(D, 4, n_p, n_c)
     achieved = pb / (r32["push_ms"] * 1e-3) / 1e9
+    copy_gbs = copy_bandwidth()
     out = {
         "metric": METRIC,
         "value": value,
@@ -536,10 +560,11 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": MEASURED_PUSH_TRAFFIC.get((kernel_source_hash(), "fp32", tile32, args.n, args.ppc)),
                      "kernel": "k_push<float,2,fused>", "push_ms": r32["push_ms"],
-                     "algorithmic_bytes_per_launch": pb, "kernel_sources": kernel_source_hash()},
+                     "algorithmic_bytes_per_launch": pb, "kernel_sources": kernel_source_hash(),
+                     "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "step_roofline_frac": algorithmic_bytes(D, 4, n_p, n_c) * value / n_p / 1e9 / HBM_PEAK_GBS,
-        "diagnostics_fp32": {k: r32["diag"][k] for k in ("gauss_max", "divb_max", "field_energy",
-                                                         "kinetic_energy", "particles", "status")},
+        "diagnostics_fp32": {k: r32["diag"][k] for k in ("gauss_max", "continuity_max", "divb_max", "field_energy",
+                                                         "kinetic_energy", "particles", "near_face", "status")},
         "cpu_baseline": cpu,
         "fp32_vs_oracle_1step_rel_l2": err32,
     }
@@ -548,7 +573,8 @@ def main():
         out["fp64"] = {"value": v64, "ms_per_step": r64["seconds"] / args.steps * 1e3,
                        "push_ms": r64["push_ms"], "speedup_fp32_over_fp64": value / v64,
                        "tile": tile64, "autotune_ms_per_step": tune64,
-                       "gauss_max": r64["diag"]["gauss_max"], "status": r64["diag"]["status"],
+                       "gauss_max": r64["diag"]["gauss_max"], "continuity_max": r64["diag"]["continuity_max"],
+                       "status": r64["diag"]["status"],
                        "vs_oracle_1step_rel_l2": err64}
     print(json.dumps(out), flush=True)
 

@@ -155,9 +155,12 @@ typedef struct {
  * wall plane (it carries the conductor's surface charge). */
 #define PIC_WALL_X 1
 
-/* pic_config.options: accumulate the tile current block in LDS in the
- * working precision instead of FP64 (the default; the block is rounded to
- * the working precision once when it is written out). */
+/* pic_config.options: accumulate the fused push's current block in LDS in
+ * the working precision.  Without it (the default) an FP64 run accumulates
+ * in FP64 and an FP32 run in 64-bit fixed point (each ZigZag value scaled
+ * by 2^e with |q| 2^e < 2^30 and rounded to an integer, the sum exact and
+ * independent of the order of the atomics); the block is converted to the
+ * working precision once when it is written out. */
 #define PIC_OPT_ACC_WORKING 1u
 /* pic_config.options: run the push as a persistent tile walker (a grid of
  * resident work-groups pulls tiles, heaviest first, from an atomic counter)

@@ -446,7 +446,7 @@ struct Impl {
         if constexpr (FUSED) {
             if (x->walls) return push_launch<FUSED, HALFB, A, 0, true, pic::PUSHER_BORIS>(x);
         }
-        if constexpr (FUSED && std::is_same<A, double>::value) {
+        if constexpr (FUSED && (std::is_same<A, double>::value || std::is_same<A, long long>::value)) {
             bool cubic = true;
             for (int d = 1; d < D; ++d) cubic = cubic && x->T[d] == x->T[0];
             if (cubic && x->T[0] == 8) return push_launch<FUSED, HALFB, A, 8, false, pic::PUSHER_BORIS>(x);
@@ -461,7 +461,9 @@ struct Impl {
     {
         if (!fused) return halfb ? push_with<false, true, R>(x) : push_with<false, false, R>(x);
         if (x->acc_working) return halfb ? push_with<true, true, R>(x) : push_with<true, false, R>(x);
-        return halfb ? push_with<true, true, double>(x) : push_with<true, false, double>(x);
+        // FP32: 64-bit fixed-point current block; FP64: FP64 block
+        using Acc = typename std::conditional<sizeof(R) == 4, long long, double>::type;
+        return halfb ? push_with<true, true, Acc>(x) : push_with<true, false, Acc>(x);
     }
 
     static pic_status deposit(pic_ctx *x, bool unfused_part)

@@ -204,12 +204,21 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int w, unsig
     const int G = U * blockDim.x;
     int parity = 0;
     int32_t errs = 0;
+    int fx = 0;          // fixed-point exponent of the current block
+    R qd;
     {
         const int ts = w;
         const int64_t so = p.seg_off[ts];
         const int cnt = p.seg_cnt[ts];
         const R q = p.charge[td.box * p.nspecies + s];
         const R sq = p.qm[td.box * p.nspecies + s];
+        // charge of the deposit: scaled by 2^e for a fixed-point block
+        if constexpr (std::is_same<A, long long>::value) {
+            fx = fixed_exponent(q);
+            qd = ldexp(q, fx);
+        } else {
+            qd = q;
+        }
         // uniform per-species base pointers (segment and outbox planes);
         // particle slots are 32-bit byte offsets from them (segment and
         // outbox capacities are bounded so that they fit)
@@ -284,8 +293,8 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int w, unsig
                     if (finite3<R>(u[j]) && moved_ok<R, D>(x2[j], dv, T)) {
                         if constexpr (FUSED) {
                             bool done = false;
-                            if constexpr (WALLS) done = wall_reflect<R, D, A>(sJ, cb, T, td.walls, x[j], x2[j], u[j], dv, q);
-                            if (!done) zigzag<R, D, A>(sJ, cb, T, x[j], x2[j], dv, q);
+                            if constexpr (WALLS) done = wall_reflect<R, D, A>(sJ, cb, T, td.walls, x[j], x2[j], u[j], dv, qd);
+                            if (!done) zigzag<R, D, A>(sJ, cb, T, x[j], x2[j], dv, qd);
                             code[j] = direction_code<R, D>(x2[j], T, delta[j]);
                         }
                     } else {
@@ -367,7 +376,12 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int w, unsig
     if constexpr (FUSED) {
         __syncthreads();
         R *blk = p.jblk + (int64_t)w * 3 * cb.n;
-        for (int k = threadIdx.x; k < 3 * cb.n; k += blockDim.x) blk[k] = (R)sJ[k];
+        if constexpr (std::is_same<A, long long>::value) {
+            const double inv = ldexp(1.0, -fx);
+            for (int k = threadIdx.x; k < 3 * cb.n; k += blockDim.x) blk[k] = (R)((double)sJ[k] * inv);
+        } else {
+            for (int k = threadIdx.x; k < 3 * cb.n; k += blockDim.x) blk[k] = (R)sJ[k];
+        }
     }
 }
 
