@@ -11,6 +11,12 @@ namespace pic {
 
 constexpr int MAX_WAVES = 16;
 
+// groups of particles the push loads ahead of the one it works on (2 and 3
+// measured no faster than 1 on the 2D FP32 and FP64 push and cost registers)
+#ifndef PUSH_PREFETCH
+#define PUSH_PREFETCH 1
+#endif
+
 // Exclusive prefix of a per-thread flag over the whole work-group (wave
 // ballots, then per-wave totals in LDS).  sTot holds 2*MAX_WAVES ints and the
 // two halves alternate by `parity`, so one barrier per call suffices.
@@ -234,21 +240,25 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int w, unsig
         }
         int32_t *const OD = p.ob_dir + (int64_t)ts * p.ob_dir_stride;
         int keep = 0, nleave = 0;
-        // next group's particles, loaded one group ahead.  Segment
-        // capacities are multiples of the group size, so every lane of a
-        // group indexes a slot of the segment (lanes past the count read
-        // and write free slots): loads and stores need no branch.
-        R nx[U][3], nu[U][3];
+        // the particles of the next PF groups, loaded PF groups ahead.
+        // Segment capacities are multiples of the group size, so every lane
+        // of a group indexes a slot of the segment (lanes past the count read
+        // free slots): loads need no branch.
+        constexpr int PF = PUSH_PREFETCH;
+        R nx[PF][U][3], nu[PF][U][3];
 #pragma unroll
-        for (int j = 0; j < U; ++j) {
+        for (int g = 0; g < PF; ++g) {
 #pragma unroll
-            for (int d = 0; d < 3; ++d) nx[j][d] = nu[j][d] = R(0);
-            if (cnt > 0) {
-                const uint32_t o = (uint32_t)(j * (int)blockDim.x + (int)threadIdx.x) * (uint32_t)sizeof(R);
+            for (int j = 0; j < U; ++j) {
 #pragma unroll
-                for (int d = 0; d < D; ++d) nx[j][d] = ld_off(X[d], o);
+                for (int d = 0; d < 3; ++d) nx[g][j][d] = nu[g][j][d] = R(0);
+                if (g * G < cnt) {
+                    const uint32_t o = (uint32_t)(g * G + j * (int)blockDim.x + (int)threadIdx.x) * (uint32_t)sizeof(R);
 #pragma unroll
-                for (int m = 0; m < 3; ++m) nu[j][m] = ld_off(V[m], o);
+                    for (int d = 0; d < D; ++d) nx[g][j][d] = ld_off(X[d], o);
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) nu[g][j][m] = ld_off(V[m], o);
+                }
             }
         }
         for (int c0 = 0; c0 < cnt; c0 += G) {
@@ -259,22 +269,31 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int w, unsig
                 valid[j] = c0 + j * (int)blockDim.x + (int)threadIdx.x < cnt;
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    x[j][d] = nx[j][d];
-                    u[j][d] = nu[j][d];
+                    x[j][d] = nx[0][j][d];
+                    u[j][d] = nu[0][j][d];
                     x2[j][d] = x[j][d];
                 }
             }
-            // prefetch: the next group lies beyond every element this group
+#pragma unroll
+            for (int g = 0; g + 1 < PF; ++g)
+#pragma unroll
+                for (int j = 0; j < U; ++j)
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        nx[g][j][d] = nx[g + 1][j][d];
+                        nu[g][j][d] = nu[g + 1][j][d];
+                    }
+            // prefetch: later groups lie beyond every element this group
             // writes (compaction only moves elements down)
-            if (c0 + G < cnt) {
+            if (c0 + PF * G < cnt) {
 #pragma unroll
                 for (int j = 0; j < U; ++j) {
                     const uint32_t o =
-                        (uint32_t)(c0 + G + j * (int)blockDim.x + (int)threadIdx.x) * (uint32_t)sizeof(R);
+                        (uint32_t)(c0 + PF * G + j * (int)blockDim.x + (int)threadIdx.x) * (uint32_t)sizeof(R);
 #pragma unroll
-                    for (int d = 0; d < D; ++d) nx[j][d] = ld_off(X[d], o);
+                    for (int d = 0; d < D; ++d) nx[PF - 1][j][d] = ld_off(X[d], o);
 #pragma unroll
-                    for (int m = 0; m < 3; ++m) nu[j][m] = ld_off(V[m], o);
+                    for (int m = 0; m < 3; ++m) nu[PF - 1][j][m] = ld_off(V[m], o);
                 }
             }
             int delta[U][3], code[U];
