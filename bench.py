@@ -88,6 +88,8 @@ def parse():
     ap.add_argument("--fd", action="store_true", help="shear-adjoint: also central differences of the FP64 forward")
     ap.add_argument("--shock-blocks", type=lambda v: [int(b) for b in v.split(",")], default=[256, 512, 1024],
                     help="shock: work-group sizes of the per-tile push to try")
+    ap.add_argument("--shock-tile", type=lambda v: tuple(int(b) for b in v.split(",")), default=(8, 8, 8),
+                    help="shock: tile edges (x, y, z)")
     ap.add_argument("--pusher", default="boris", choices=["boris", "vay", "hc"],
                     help="turbulence: particle pusher of the timed runs")
     ap.add_argument("--filter-passes", type=int, default=0,
@@ -334,7 +336,7 @@ def bench_shock(args):
     t0 = time.perf_counter()
     plasma = synth.shock(log=log)
     n_p, n_c, D = plasma.nparticles, plasma.ncells, 3
-    T = (8, 8, 8)
+    T = tuple(args.shock_tile)
     log(f"generated {n_p} particles in {time.perf_counter() - t0:.1f}s")
     results = {}
     runs = [(f"per_tile_b{b}", 0, b) for b in args.shock_blocks] + [("persistent", L.PIC_OPT_PERSISTENT, None)]
