@@ -65,7 +65,9 @@ def parse():
     ap.add_argument("--n", type=int, default=1024, help="cells per side")
     ap.add_argument("--ppc", type=int, default=16, help="particles per cell per species")
     ap.add_argument("--tile", default="auto", help="tile edge, or 'auto' (autotuner over 8/16/32)")
-    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--block", type=int, default=0,
+                    help="work-group size of the particle kernels; 0: the autotuner picks 128, 256 or 512 "
+                         "(256 when the tile is given)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -115,12 +117,12 @@ def push_bytes(D, w, n_particles, n_cells):
     return n_particles * 2 * (D + 3) * w + n_cells * 9 * w
 
 
-def run_gpu(plasma, args, precision, steps, warmup, tile, profile_only=False):
+def run_gpu(plasma, args, precision, steps, warmup, tile, block=256, profile_only=False):
     import torch
     from paper_1906_06306_amd import _lib as L
     from paper_1906_06306_amd.sim import PicSim
 
-    sim = PicSim(plasma, tile=(tile, tile), precision=precision, block=args.block,
+    sim = PicSim(plasma, tile=(tile, tile), precision=precision, block=block,
                  capacity_factor=args.capacity, pusher=args.pusher, filter_passes=args.filter_passes,
                  fdtd_order=args.fdtd_order)
     stream = torch.cuda.current_stream()
@@ -169,6 +171,7 @@ def run_gpu(plasma, args, precision, steps, warmup, tile, profile_only=False):
     # discrete continuity residual of a step
     step()
     diag = sim.diagnostics()
+    diag["max_segment_fill"] = sim.fill_ratio()
     sim.close()
     del sim
     torch.cuda.empty_cache()
@@ -208,11 +211,13 @@ def one_step_error(plasma, precision, tile, ref):
 
 
 def pick_tile(plasma, args, precision):
+    """(tile edge, work-group size, autotuner timings or None)."""
     if args.tile != "auto":
-        return int(args.tile), None
+        return int(args.tile), args.block or 256, None
     from paper_1906_06306_amd import autotune
-    (T, _), res = autotune.tune(plasma, precision, blocks=(args.block,), capacity_factor=args.capacity, log=log)
-    return T, {f"T{k[0]}_b{k[1]}": round(v * 1e3, 4) for k, v in res.items()}
+    blocks = (args.block,) if args.block else (128, 256, 512)
+    (T, blk), res = autotune.tune(plasma, precision, blocks=blocks, capacity_factor=args.capacity, log=log)
+    return T, blk, {f"T{k[0]}_b{k[1]}": round(v * 1e3, 4) for k, v in res.items()}
 
 
 def copy_bandwidth():
@@ -507,17 +512,17 @@ def main():
     n_p, n_c, D = plasma.nparticles, plasma.ncells, plasma.D
     if args.profile_steps:
         tile = 16 if args.tile == "auto" else int(args.tile)
-        code = run_gpu(plasma, args, args.precision, args.profile_steps, 0, tile, profile_only=True)
+        code = run_gpu(plasma, args, args.precision, args.profile_steps, 0, tile, args.block or 256, profile_only=True)
         log(f"profile run done, device status {code}")
         return
-    tile32, tune32 = pick_tile(plasma, args, "fp32")
-    log(f"fp32 run, tile {tile32}")
-    r32 = run_gpu(plasma, args, "fp32", args.steps, args.warmup, tile32)
+    tile32, blk32, tune32 = pick_tile(plasma, args, "fp32")
+    log(f"fp32 run, tile {tile32}, block {blk32}")
+    r32 = run_gpu(plasma, args, "fp32", args.steps, args.warmup, tile32, blk32)
     r64 = None
     if not args.no_fp64:
-        tile64, tune64 = pick_tile(plasma, args, "fp64")
-        log(f"fp64 run, tile {tile64}")
-        r64 = run_gpu(plasma, args, "fp64", args.steps, args.warmup, tile64)
+        tile64, blk64, tune64 = pick_tile(plasma, args, "fp64")
+        log(f"fp64 run, tile {tile64}, block {blk64}")
+        r64 = run_gpu(plasma, args, "fp64", args.steps, args.warmup, tile64, blk64)
     cpu = None
     err32 = err64 = None
     if not args.no_cpu:
@@ -555,7 +560,7 @@ def main():
         "config": {"workload": f"2D3V decaying turbulence {args.n}x{args.n} periodic, "
                                f"{args.ppc} ppc/species pair plasma, "
                                "theta=0.3, sigma=10, dB/B0=1 (64 modes), c/w_p=3 cells, Courant 0.45",
-                   "particles": n_p, "cells": n_c, "tile": tile32, "block": args.block,
+                   "particles": n_p, "cells": n_c, "tile": tile32, "block": blk32,
                    "pusher": args.pusher, "filter_passes": args.filter_passes, "fdtd_order": args.fdtd_order,
                    "autotune_ms_per_step": tune32},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -566,7 +571,8 @@ def main():
                      "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "step_roofline_frac": algorithmic_bytes(D, 4, n_p, n_c) * value / n_p / 1e9 / HBM_PEAK_GBS,
         "diagnostics_fp32": {k: r32["diag"][k] for k in ("gauss_max", "continuity_max", "divb_max", "field_energy",
-                                                         "kinetic_energy", "particles", "near_face", "status")},
+                                                         "kinetic_energy", "particles", "near_face",
+                                                         "max_segment_fill", "status")},
         "cpu_baseline": cpu,
         "fp32_vs_oracle_1step_rel_l2": err32,
     }
@@ -574,7 +580,7 @@ def main():
         v64 = n_p * args.steps / r64["seconds"]
         out["fp64"] = {"value": v64, "ms_per_step": r64["seconds"] / args.steps * 1e3,
                        "push_ms": r64["push_ms"], "speedup_fp32_over_fp64": value / v64,
-                       "tile": tile64, "autotune_ms_per_step": tune64,
+                       "tile": tile64, "block": blk64, "autotune_ms_per_step": tune64,
                        "gauss_max": r64["diag"]["gauss_max"], "continuity_max": r64["diag"]["continuity_max"],
                        "status": r64["diag"]["status"],
                        "vs_oracle_1step_rel_l2": err64}

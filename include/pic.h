@@ -162,10 +162,9 @@ typedef struct {
  * independent of the order of the atomics); the block is converted to the
  * working precision once when it is written out. */
 #define PIC_OPT_ACC_WORKING 1u
-/* pic_config.options: run the push as a persistent tile walker (a grid of
- * resident work-groups pulls tiles, heaviest first, from an atomic counter)
- * instead of one work-group per tile; for uneven tile loads and batches of
- * boxes of different sizes. */
+/* pic_config.options: run the push as a persistent walker (a grid of
+ * resident work-groups pulls (tile, species) segments, largest first, from
+ * an atomic counter) instead of one work-group per segment. */
 #define PIC_OPT_PERSISTENT 2u
 /* pic_config.options: origin tracking for the reverse-mode adjoint.  Every
  * fused step (and pic_init_tiles) records, per stored particle, where it
@@ -261,15 +260,18 @@ pic_status pic_fdtd_step(pic_ctx *ctx, int32_t phase);
  * Boris update of u (App. C), position advance x += c u/gamma (Eq. fdX).
  * Without PIC_FUSED the new positions are stored in place unrebased and
  * the old ones in the xold region, for pic_deposit_current and
- * pic_sort_migrate.  With PIC_FUSED the same work-group also deposits the
- * ZigZag current of every particle into its tile's current block (App. D)
- * and compacts the particles that stay, moving leavers to the tile outbox
- * (the "tag outflowing / pack" rows of Table 1). */
+ * pic_sort_migrate.  One work-group handles one (tile, species) segment;
+ * the segments are visited in decreasing particle count (re-sorted on the
+ * device at every call).  With PIC_FUSED the same work-group also deposits
+ * the ZigZag current of its particles into the segment's current block
+ * (App. D) and compacts the particles that stay, moving leavers to the
+ * segment's outbox (the "tag outflowing / pack" rows of Table 1). */
 pic_status pic_push_interp(pic_ctx *ctx, uint32_t flags);
 
 /* comp_curr + clear_vir_cur + cur_exchange: after an unfused push, ZigZag
- * deposit from (xold, x) into per-tile current blocks; in both modes, sum
- * the blocks (tile plus halo) into J on the lattice. */
+ * deposit from (xold, x) into per-segment current blocks; in both modes, sum
+ * the blocks (every species of the tile plus the halos of its neighbours)
+ * into J on the lattice, in a fixed order. */
 pic_status pic_deposit_current(pic_ctx *ctx, uint32_t flags);
 
 /* Particle communication rows of Table 1: after an unfused push, move the

@@ -3,7 +3,7 @@ the actual workload and keeps the fastest.
 
 Tile size matters for the method (the paper reports a 2x spread in wall time
 between tile sizes for one run, Sect. 6 footnote); on gfx950 the trade-off is
-LDS per work-group (fields, halo and the FP64 current block grow as T^D)
+LDS per work-group (fields, halo and the 8-byte current block grow as T^D)
 against halo overhead and the number of work-groups.
 """
 from __future__ import annotations
@@ -30,7 +30,7 @@ def time_step(sim: PicSim, steps: int = 4, warmup: int = 2, flags: int = L.PIC_F
 
 
 def lds_bytes(D: int, T: int, elem: int) -> int:
-    """LDS of the fused push for edge T: E (T+3)^D, B (T+2)^D, FP64 J (T+3)^D."""
+    """LDS of the fused push for edge T: E (T+3)^D, B (T+2)^D, 8-byte J (T+3)^D."""
     return 3 * (T + 3) ** D * elem + 3 * (T + 2) ** D * elem + 3 * (T + 3) ** D * 8
 
 

@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(ORDER_BUCKETS) k_order(const int32_t *cnt, int
     hist[tid] = 0;
     __syncthreads();
     for (int w = tid; w < n; w += ORDER_BUCKETS)
-        atomicAdd(&hist[ORDER_BUCKETS - 1 - min(cnt[w] >> shift, ORDER_BUCKETS - 1)], 1);
+        atomicAdd(&hist[ORDER_BUCKETS - 1 - min(max(cnt[w], 0) >> shift, ORDER_BUCKETS - 1)], 1);
     __syncthreads();
     // exclusive prefix over the buckets: wave scans, then the wave totals
     const int v = hist[tid];
@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(ORDER_BUCKETS) k_order(const int32_t *cnt, int
     hist[tid] = x - v + wsum[wv];
     __syncthreads();
     for (int w = tid; w < n; w += ORDER_BUCKETS) {
-        const int pos = atomicAdd(&hist[ORDER_BUCKETS - 1 - min(cnt[w] >> shift, ORDER_BUCKETS - 1)], 1);
+        const int pos = atomicAdd(&hist[ORDER_BUCKETS - 1 - min(max(cnt[w], 0) >> shift, ORDER_BUCKETS - 1)], 1);
         order[pos] = w;
     }
 }

@@ -331,6 +331,15 @@ class PicSim:
         J = self._view(self.layout.off_J, 3 * N, self.dtype).view(3, N)
         return E, B, J
 
+    def fill_ratio(self) -> float:
+        """Largest count / capacity over the (tile, species) segments: the
+        headroom left before a push or migration would latch
+        PIC_E_CAPACITY."""
+        nts = int(self.layout.tiles_total) * self.ns
+        cap = self._view(self.layout.off_seg_capacity, nts, torch.int32).float()
+        cnt = self._view(self.layout.off_seg_count, nts, torch.int32).float()
+        return float((cnt / cap).max().item())
+
     def particle_views(self):
         cap = int(self.layout.capacity_total)
         pos = self._view(self.layout.off_pos, self.D * cap, self.dtype).view(self.D, cap)
