@@ -50,6 +50,10 @@ class PicSim:
         if not isinstance(boxes, (list, tuple)):
             boxes = [boxes]
         boxes = [b if isinstance(b, Box) else box_from_plasma(b) for b in boxes]
+        # settings a re-layout (regrow) repeats
+        self._kw = dict(tile=tile, precision=precision, block=block, outbox_capacity=outbox_capacity,
+                        options=options, device=device, stream=stream, walls=walls, pusher=pusher,
+                        filter_passes=filter_passes, fdtd_order=fdtd_order, inject_max=inject_max)
         self.boxes = boxes
         b0 = boxes[0]
         self.D = b0.D
@@ -380,6 +384,43 @@ class PicSim:
         if with_xold:
             out.append(xold[:, it].cpu().numpy())
         return tuple(out)
+
+    def state_boxes(self) -> list:
+        """The current state as FP64 `Box` objects, particles in storage
+        order.  Exact: a tile-local coordinate in the working precision plus
+        its tile centre (an integer) is an FP64 sum without rounding, and
+        binning that global position gives back the same tile and local
+        coordinate."""
+        out = []
+        for i, b in enumerate(self.boxes):
+            E, B, _ = self.fields_host(i)
+            pos, us = [], []
+            for s in range(self.ns):
+                tid, xl, u = self.particles_host(i, s)
+                nt = self.nt[i]
+                tc = [tid % nt[0], (tid // nt[0]) % nt[1], tid // (nt[0] * nt[1])]
+                x = np.empty((self.D, tid.size))
+                for d in range(self.D):
+                    x[d] = tc[d] * self.T[d] + self.T[d] // 2 + xl[d].astype(np.float64)
+                pos.append(x)
+                us.append(u.astype(np.float64))
+            out.append(Box(D=b.D, n=tuple(b.n), c=b.c, charge=list(b.charge), qm=list(b.qm), mass=list(b.mass),
+                           pos=pos, u=us, E=E, B=B))
+        return out
+
+    def regrow(self, factor: float = 2.0) -> "PicSim":
+        """A new simulation holding this one's state, with segment capacities
+        of factor x the current counts (dilated over neighbouring tiles, as
+        `tile_capacity="auto"`).  For runs whose plasma compresses beyond the
+        capacities chosen at the start (`fill_ratio` tells the headroom).  A
+        host round trip of the whole state: meant for occasional use.  The
+        caller closes the old simulation.  Origin ids (`PIC_OPT_TRACK`) do not
+        carry over, so tracked runs are refused."""
+        if self.cfg.options & L.PIC_OPT_TRACK:
+            raise ValueError("origin ids do not carry over a re-layout")
+        kw = dict(self._kw)
+        kw.update(tile_capacity="auto", capacity_factor=factor)
+        return PicSim(self.state_boxes(), **kw)
 
     def counts_host(self):
         torch.cuda.synchronize(self.device)

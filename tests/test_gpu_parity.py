@@ -194,6 +194,30 @@ def test_fp32_runs_are_bit_reproducible():
         r.close()
 
 
+def test_regrow_continues_the_run_bit_for_bit():
+    """A re-layout with larger segments (PicSim.regrow) holds the same state
+    and, the FP32 current being exact, continues the run bit for bit."""
+    plasma = synth.small_random(2, (64, 48), 4, seed=91, field_amp=0.05)
+    sim = make_sim(plasma, (8, 8), "fp32", capacity_factor=1.5)
+    sim.step(3, half_b_in_push=True)
+    fill = sim.fill_ratio()
+    big = sim.regrow(4.0)
+    assert 0 < big.fill_ratio() < fill
+    for x, y in zip(sim.fields_host(0)[:2], big.fields_host(0)[:2]):
+        assert np.array_equal(x, y)
+    for s in range(2):
+        assert all(np.array_equal(a, b) for a, b in zip(sim.particles_host(0, s), big.particles_host(0, s)))
+    sim.step(2, half_b_in_push=True)
+    big.step(2, half_b_in_push=True)
+    for x, y in zip(sim.fields_host(0), big.fields_host(0)):
+        assert np.array_equal(x, y)
+    for s in range(2):
+        assert all(np.array_equal(a, b) for a, b in zip(sim.particles_host(0, s), big.particles_host(0, s)))
+    assert sim.error() == 0 and big.error() == 0
+    sim.close()
+    big.close()
+
+
 @pytest.mark.parametrize("persistent", [False, True])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_uneven_segments_match_oracle(prec, persistent):
