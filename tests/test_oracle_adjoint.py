@@ -1,6 +1,6 @@
 """Pins of the oracle's hand-written adjoint (reverse mode) of the step.
 
-Differentiation is this build's addition (the paper integrates forward
+Differentiation is an addition to the method (the paper integrates forward
 only); the adjoint must be the exact vector-Jacobian product of the forward
 step, so it is pinned against central finite differences of the forward
 oracle in random directions of the whole state (1D/2D/3D), against the
