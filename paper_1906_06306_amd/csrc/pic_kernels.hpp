@@ -843,34 +843,48 @@ __global__ void __launch_bounds__(1024) k_migrate_in(Params<R> p)
         const int64_t so = p.seg_off[ts];
         const int scap = p.seg_cap[ts];
         const int cnt = p.seg_cnt[ts];
-        if ((int)threadIdx.x < NC) {
+        // the first wave: bucket sizes of the neighbours and their prefix
+        // (a wave scan), one barrier
+        if (threadIdx.x < 64) {
             const int code = threadIdx.x;
-            int nc[3] = {0, 0, 0}, rem = code;
+            int n_in = 0;
+            if (code < NC) {
+                int nc[3] = {0, 0, 0}, rem = code;
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                if (d < D) {
-                    const int delta = rem % 3 - 1;
-                    rem /= 3;
-                    nc[d] = wrapi(td.tc[d] - delta, td.nt[d]);
+                for (int d = 0; d < 3; ++d) {
+                    if (d < D) {
+                        const int delta = rem % 3 - 1;
+                        rem /= 3;
+                        const int v = td.tc[d] - delta;   // source tile, periodic (one step at most)
+                        nc[d] = v < 0 ? v + td.nt[d] : (v >= td.nt[d] ? v - td.nt[d] : v);
+                    }
                 }
+                const int sts = (td.tile0 + nc[0] + td.nt[0] * (nc[1] + td.nt[1] * nc[2])) * p.nspecies + s;
+                const int32_t *boff = p.ob_boff + (int64_t)sts * (NC + 1);
+                sSrc[code] = sts;
+                sB0[code] = boff[code];
+                n_in = code == centre_code<D>() ? 0 : boff[code + 1] - boff[code];
             }
-            const int sts = (td.tile0 + nc[0] + td.nt[0] * (nc[1] + td.nt[1] * nc[2])) * p.nspecies + s;
-            const int32_t *boff = p.ob_boff + (int64_t)sts * (NC + 1);
-            sSrc[code] = sts;
-            sB0[code] = boff[code];
-            sOff[code + 1] = code == centre_code<D>() ? 0 : boff[code + 1] - boff[code];
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            sOff[0] = 0;
-            for (int k = 0; k < NC; ++k) sOff[k + 1] += sOff[k];
+            int x = n_in;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(x, o, 64);
+                if (code >= o) x += y;
+            }
+            if (code < NC) sOff[code + 1] = x;
+            if (code == 0) sOff[0] = 0;
         }
         __syncthreads();
         const int total = sOff[NC];
         int32_t errs = 0;
         for (int e = threadIdx.x; e < total; e += blockDim.x) {
-            int code = 0;
-            while (sOff[code + 1] <= e) ++code;
+            // code of element e: the first bucket whose end lies beyond e
+            int code = 0, hi = NC - 1;
+            while (code < hi) {
+                const int mid = (code + hi) >> 1;
+                if (sOff[mid + 1] <= e) code = mid + 1;
+                else hi = mid;
+            }
             const int64_t sts = sSrc[code];
             const int64_t k = p.ob_idx[sts * p.ob_cap + sB0[code] + (e - sOff[code])];
             const int dst = cnt + e;
