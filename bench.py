@@ -81,7 +81,7 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale rocprofv3 FETCH/WRITE_SIZE)")
     ap.add_argument("--workload", default="turbulence",
-                    choices=["turbulence", "shear-adjoint", "shock", "ensemble"],
+                    choices=["turbulence", "shear-adjoint", "shock", "ensemble", "weibel"],
                     help="turbulence: the throughput line; shear-adjoint: the differentiable window "
                          "(256^2, 32 ppc/species, 40 steps, checkpoints every 8) with its forward and "
                          "reverse rates and gradients; shock: 3D3V pre-shocked plasma between walls, "
@@ -100,7 +100,7 @@ def parse():
                     help="turbulence: FDTD2 (App. B) or FDTD4")
     args = ap.parse_args()
     if args.steps is None:
-        args.steps = {"turbulence": 500, "ensemble": 100}.get(args.workload, 50)
+        args.steps = {"turbulence": 500, "ensemble": 100, "weibel": 200}.get(args.workload, 50)
     return args
 
 
@@ -406,6 +406,90 @@ def bench_shock(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_weibel(args):
+    """1D3V two-stream (Weibel-shaped) pair plasma, FP64: 512 cells, 64
+    ppc/species, the whole 200-step run on the GPU and in the oracle (one
+    host thread), with the final fields compared.  Cache-resident (a few MB):
+    a rate, no roofline.  One JSON line (not the headline metric)."""
+    import torch
+    import synth
+    import oracle
+    from paper_1906_06306_amd import _lib as L
+    from paper_1906_06306_amd.sim import PicSim
+
+    plasma = synth.weibel()
+    n_p = plasma.nparticles
+    flags = L.PIC_FUSED | L.PIC_PUSH_HALF_B
+    lib = L.lib()
+
+    def rate(T, steps):
+        sim = PicSim(plasma, tile=(T,), precision="fp64", capacity_factor=2.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            L.check(lib.pic_step(sim.ctx, flags))
+        torch.cuda.synchronize()
+        sim.close()
+        return (time.perf_counter() - t0) / steps
+
+    # tile edge: at 65,536 particles more, smaller segments keep more of the
+    # chip busy, against more halo work
+    tune = {T: rate(T, 20) for T in ((int(args.tile),) if args.tile != "auto" else (8, 16, 32))}
+    T = min(tune, key=tune.get)
+    # eager launches; at 65,536 particles a step is a handful of short
+    # kernels, so launch overhead counts
+    sim = PicSim(plasma, tile=(T,), precision="fp64", capacity_factor=2.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        L.check(lib.pic_step(sim.ctx, flags))
+    torch.cuda.synchronize()
+    eager_s = time.perf_counter() - t0
+    sim.close()
+    # the step captured in a HIP graph (capture runs one eager step, then
+    # the graph replays the other steps)
+    stream = torch.cuda.Stream()
+    sim = PicSim(plasma, tile=(T,), precision="fp64", capacity_factor=2.0, stream=stream)
+    sim.capture(1, fused=True, half_b_in_push=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.replay(args.steps - 1)
+    torch.cuda.synchronize()
+    graph_s = (time.perf_counter() - t0) * args.steps / (args.steps - 1)
+    gpu_s = min(eager_s, graph_s)
+    d = sim.diagnostics()
+    E, _, _ = sim.fields_host(0)
+    L.check(lib.pic_step(sim.ctx, flags))      # one more step: its continuity residual
+    d["continuity_max"] = sim.diagnostics()["continuity_max"]
+    sim.close()
+    if d["status"] != 0:
+        raise SystemExit(f"device status {d['status']} after the Weibel run: the measurement is invalid")
+    st = oracle.State(plasma)
+    t0 = time.perf_counter()
+    st.step(args.steps)
+    cpu_s = time.perf_counter() - t0
+    nrm = np.linalg.norm(st.E)
+    out = {
+        "metric": "particle-steps/s (push+deposit+FDTD) FP64 at 1 GPU, 1D two-stream",
+        "value": n_p * args.steps / gpu_s, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 0, "ms_per_step": gpu_s / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "1D3V pair plasma, 512 cells, 64 ppc/species, counter-streaming beams gamma=3, "
+                               "theta=0.01, c/w_p=10 cells, Courant 0.45", "particles": n_p,
+                   "steps": args.steps, "tile": T,
+                   "autotune_ms_per_step": {f"T{k}": round(v * 1e3, 4) for k, v in tune.items()}},
+        "roofline": None,
+        "ms_per_step_eager": eager_s / args.steps * 1e3, "ms_per_step_graph": graph_s / args.steps * 1e3,
+        "gauss_max": d["gauss_max"], "continuity_max": d["continuity_max"],
+        "field_energy": d["field_energy"],
+        "vs_oracle_final_rel_l2_E": float(np.linalg.norm(E - st.E) / (nrm if nrm > 0 else 1.0)),
+        "cpu_baseline": {"value": n_p * args.steps / cpu_s, "unit": "particle-steps/s", "cores": 1,
+                         "kind": "oracle", "sample": f"the whole {args.steps}-step run, single-threaded FP64 C "
+                                                     f"oracle, {cpu_s:.1f} s"},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_ensemble(args):
     """64 independent 2D3V thermal boxes of uneven sizes stepped together:
     autotuned tile edge, per-tile launch vs persistent walker, eager vs a
@@ -505,6 +589,9 @@ def main():
         return
     if args.workload == "ensemble":
         bench_ensemble(args)
+        return
+    if args.workload == "weibel":
+        bench_weibel(args)
         return
     t0 = time.perf_counter()
     plasma = synth.turbulence(n=args.n, ppc=args.ppc)
