@@ -151,7 +151,7 @@ pic_status make_layout(const pic_config *c, const int64_t *counts, Layout &L)
             L.max_count = std::max<int64_t>(L.max_count, c->inject_max);
         }
     }
-    if (L.max_ntb > 32768) return fail(PIC_E_ARG, "a box has %lld tiles; at most 32768 are supported", (long long)L.max_ntb);
+    if (L.max_ntb > (int64_t(1) << 24)) return fail(PIC_E_ARG, "a box has %lld tiles; at most 2^24 are supported", (long long)L.max_ntb);
     if (tiles > INT32_MAX / 8) return fail(PIC_E_ARG, "too many tiles");
     // segment capacities: a multiple of the push kernel's group (threads x
     // particles per thread), so every lane of the last group of a segment
@@ -547,8 +547,13 @@ struct Impl {
         int kgrid = (int)std::min<int64_t>((count + 255) / 256, 16384);
         hipLaunchKernelGGL((pic::k_bin_keys<R, D>), dim3(kgrid), dim3(256), 0, x->stream, g, pos, key, xl, p.err,
                            p.nearface);
-        size_t lds = (size_t)g.ntb * sizeof(int);
-        pic_status st = set_lds(pic::k_bin_hist, lds);
+        // per-chunk tile histograms in LDS up to 32,768 tiles per box, else
+        // in global memory (zeroed here)
+        g.hist_lds = g.ntb <= 32768;
+        size_t lds = g.hist_lds ? (size_t)g.ntb * sizeof(int) : 0;
+        pic_status st = PIC_OK;
+        if (!g.hist_lds) st = fill<int32_t>(x, hist, (int64_t)g.nchunks * g.ntb, 0);
+        if (!st) st = set_lds(pic::k_bin_hist, lds);
         if (st) return st;
         hipLaunchKernelGGL(pic::k_bin_hist, dim3(g.nchunks), dim3(256), lds, x->stream, g, key, hist);
         hipLaunchKernelGGL(pic::k_bin_scan, dim3((g.ntb + 255) / 256), dim3(256), 0, x->stream, g, hist, p.seg_cnt,

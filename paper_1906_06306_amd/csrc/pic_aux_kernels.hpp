@@ -90,6 +90,7 @@ struct BinGeom {
     int32_t chunk;        // particles per chunk
     int64_t id_base;      // origin id of input particle 0 of this (box, species)
     int32_t walls;        // the box has conducting walls at x = 0 and x = n0
+    int32_t hist_lds;     // per-chunk tile histograms fit in LDS (else they stay in global memory)
 };
 
 template <typename R>
@@ -164,15 +165,24 @@ __global__ void __launch_bounds__(256) k_hold_walls(Params<R> p)
 __global__ void k_bin_hist(BinGeom g, const int32_t *key, int32_t *hist)
 {
     extern __shared__ int sh[];
+    int32_t *row = hist + (int64_t)blockIdx.x * g.ntb;
+    const int64_t lo = (int64_t)blockIdx.x * g.chunk, hi = min(g.count, lo + g.chunk);
+    if (!g.hist_lds) {
+        // too many tiles for LDS: count straight into the (zeroed) row
+        for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+            const int k = key[i];
+            if (k >= 0) atomicAdd(&row[k], 1);
+        }
+        return;
+    }
     for (int k = threadIdx.x; k < g.ntb; k += blockDim.x) sh[k] = 0;
     __syncthreads();
-    const int64_t lo = (int64_t)blockIdx.x * g.chunk, hi = min(g.count, lo + g.chunk);
     for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
         int k = key[i];
         if (k >= 0) atomicAdd(&sh[k], 1);
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < g.ntb; k += blockDim.x) hist[(int64_t)blockIdx.x * g.ntb + k] = sh[k];
+    for (int k = threadIdx.x; k < g.ntb; k += blockDim.x) row[k] = sh[k];
 }
 
 // Chunk start offsets per tile, in (tile, chunk) order, and segment counts.
@@ -201,9 +211,15 @@ template <typename R, int D>
 __global__ void __launch_bounds__(64) k_bin_scatter(BinGeom g, const int32_t *key, const R *xl, const double *u64,
                                                     const int32_t *hist, Params<R> p, int tile0, int species)
 {
-    extern __shared__ int run[];
-    for (int k = threadIdx.x; k < g.ntb; k += 64) run[k] = hist[(int64_t)blockIdx.x * g.ntb + k];
-    __syncthreads();
+    extern __shared__ int sh[];
+    // running slot of every tile for this chunk: in LDS, or, for boxes with
+    // too many tiles, the chunk's own row of offsets in global memory (only
+    // this wave touches it; updated with atomics, which keep their order)
+    int32_t *grow = const_cast<int32_t *>(hist) + (int64_t)blockIdx.x * g.ntb;
+    if (g.hist_lds) {
+        for (int k = threadIdx.x; k < g.ntb; k += 64) sh[k] = grow[k];
+        __syncthreads();
+    }
     int nbits = 0;
     while ((1 << nbits) < g.ntb) ++nbits;
     const int64_t lo = (int64_t)blockIdx.x * g.chunk, hi = min(g.count, lo + g.chunk);
@@ -218,11 +234,18 @@ __global__ void __launch_bounds__(64) k_bin_scatter(BinGeom g, const int32_t *ke
             unsigned long long bb = __ballot((k >> b) & 1);
             m &= ((k >> b) & 1) ? bb : ~bb;
         }
-        int old = 0;
-        if (valid) old = run[k];
         const int rank = lanes_below(m);
-        const int lead = __ffsll((long long)m) - 1;
-        if (valid && lane == lead) run[k] = old + __popcll(m);
+        const int lead = valid ? __ffsll((long long)m) - 1 : lane;
+        int old = 0;
+        if (valid && lane == lead) {
+            if (g.hist_lds) {
+                old = sh[k];
+                sh[k] = old + __popcll(m);
+            } else {
+                old = atomicAdd(&grow[k], __popcll(m));
+            }
+        }
+        old = __shfl(old, lead, 64);      // the lead lane of this lane's key
         if (valid) {
             const int ts = (tile0 + k) * p.nspecies + species;
             const int slot = old + rank;

@@ -53,8 +53,11 @@ CASES = [
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("D,n,T,ppc", CASES)
+@pytest.mark.parametrize("D,n,T,ppc", CASES + [(2, (512, 320, 1), (2, 2, 1), 2)])
 def test_init_binning_bit_exact(D, n, T, ppc, prec):
+    """Binning against the oracle's rule, bit for bit; the last case has
+    40,960 tiles in its box, beyond the 32,768 whose per-chunk histograms
+    fit in LDS, so the binning kernels keep them in global memory."""
     plasma = synth.small_random(D, n, ppc, seed=3 + D)
     sim = make_sim(plasma, T, prec)
     dt = np.float64 if prec == "fp64" else np.float32
