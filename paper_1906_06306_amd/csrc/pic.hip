@@ -431,7 +431,7 @@ struct Impl {
         return PIC_OK;
     }
 
-    // The fused push with FP64 accumulation is compiled for the common cubic
+    // The fused push with the 8-byte current block is compiled for the common cubic
     // tile edges with the edge as a constant; other shapes use the
     // runtime-edge kernel.
     template <bool FUSED, bool HALFB, typename A>

@@ -74,7 +74,8 @@ __device__ __forceinline__ int wrapi(int i, int n)
     return r < 0 ? r + n : r;
 }
 
-// Tile of this work-group in launches with one work-group per tile.  The
+// Tile (or (tile, species) segment) of this work-group in launches with one
+// work-group per tile (or segment), out of n.  The
 // dispatcher hands consecutive work-groups to the eight dies (XCDs, each
 // with its own L2) in turn; this bijection gives every die a contiguous
 // range of tiles instead, so that neighbouring tiles, which share cache

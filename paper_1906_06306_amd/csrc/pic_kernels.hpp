@@ -156,10 +156,11 @@ __device__ __forceinline__ void compact_chunk(const Params<R> &p, int ts, int64_
 // ------------------------------------------------------------------ push
 
 // interp_em + push (+ comp_curr and particle pack when FUSED) for one tile.
-// The current block is accumulated in LDS in type A (FP64 by default: the
-// LDS FP64 atomic add sustains a far higher rate on gfx950 than the FP32
-// one under the many-address pattern of the deposit, and sums more
-// accurately); it is rounded to R once, at the flush.  With HALFB the
+// The current block is accumulated in LDS in type A: 64-bit fixed point for
+// FP32 runs (exact integer adds, which gfx950's LDS also runs faster than
+// its FP64 adds), FP64 for FP64 runs (the LDS FP32 atomic add is far slower
+// than either under the many-address pattern of the deposit), or R on
+// request; it is converted to R once, at the flush.  With HALFB the
 // kernel applies push_half_b1 to its LDS copy of B itself (global B stays
 // at B^{n-1/2}).  Each thread takes U particles per group (element
 // c0 + j*blockDim + t), so every load and store instruction stays
@@ -433,7 +434,7 @@ __global__ void __launch_bounds__(1024) k_push_persistent(Params<R> p)
 }
 
 // comp_curr after an unfused push: ZigZag from (xold, pos) of every
-// particle into the tile's current block.
+// particle into the segment's current block.
 template <typename R, int D, typename A>
 __global__ void __launch_bounds__(1024) k_deposit(Params<R> p)
 {
