@@ -221,12 +221,14 @@ def test_regrow_continues_the_run_bit_for_bit():
     big.close()
 
 
+@pytest.mark.parametrize("block", [128, 256, 512])
 @pytest.mark.parametrize("persistent", [False, True])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_uneven_segments_match_oracle(prec, persistent):
+def test_uneven_segments_match_oracle(prec, persistent, block):
     """Segments of very different counts (the push visits them largest first,
     one work-group per (tile, species) segment, each with its own current
-    block): three fused steps against the oracle, particle counts exact."""
+    block), at the work-group sizes the autotuner tries: three fused steps
+    against the oracle, particle counts exact."""
     from paper_1906_06306_amd import _lib as L
     plasma = synth.small_random(2, (64, 48), 4, seed=77, field_amp=0.05)
     rng = np.random.default_rng(78)
@@ -238,7 +240,7 @@ def test_uneven_segments_match_oracle(prec, persistent):
         x[0, k] = corner[0] + rng.random(int(k.sum())) * 8.0
         x[1, k] = corner[1] + rng.random(int(k.sum())) * 8.0
     T = (8, 8, 1)
-    sim = make_sim(plasma, T, prec, tile_capacity="auto", capacity_factor=1.5,
+    sim = make_sim(plasma, T, prec, tile_capacity="auto", capacity_factor=1.5, block=block,
                    options=L.PIC_OPT_PERSISTENT if persistent else 0)
     _, _, _, off, cnt = sim.particle_views()
     c = cnt.cpu().numpy()
