@@ -93,6 +93,10 @@ typedef int32_t pic_status;
 #define PIC_PUSH_HALF_B 4u  /* the push applies push_half_b1 to its own LDS
                                copy of B; stored B stays at B^{n-1/2}, and
                                the caller then uses PIC_TWO_HALF_B          */
+#define PIC_DEPOSIT_CURL_E 8u /* pic_deposit_current also applies
+                               E += c curl- B - J (push_e + add_cur, as
+                               PIC_CURL_E_ADD_J) in the fold's pass, from the
+                               folded J; FDTD2 only                         */
 
 typedef struct {
     int32_t dim;          /* spatial dimensions D in {1,2,3}                 */
@@ -271,7 +275,11 @@ pic_status pic_push_interp(pic_ctx *ctx, uint32_t flags);
 /* comp_curr + clear_vir_cur + cur_exchange: after an unfused push, ZigZag
  * deposit from (xold, x) into per-segment current blocks; in both modes, sum
  * the blocks (every species of the tile plus the halos of its neighbours)
- * into J on the lattice, in a fixed order. */
+ * into J on the lattice, in a fixed order.  With PIC_DEPOSIT_CURL_E the same
+ * pass then updates E at each cell as pic_fdtd_step(PIC_CURL_E_ADD_J) would
+ * (Eq. (fdE), same arithmetic), so the step saves that launch and the re-read
+ * of J; B must already hold B^{n+1/2}.  PIC_E_ARG with the flag under FDTD4,
+ * PIC_E_STATE without a preceding push. */
 pic_status pic_deposit_current(pic_ctx *ctx, uint32_t flags);
 
 /* Particle communication rows of Table 1: after an unfused push, move the
@@ -283,7 +291,9 @@ pic_status pic_deposit_current(pic_ctx *ctx, uint32_t flags);
 pic_status pic_sort_migrate(pic_ctx *ctx, uint32_t flags);
 
 /* One full time step in Table-1 order (see the top of this header);
- * flags as for pic_push_interp, plus PIC_SORT_CELLS. */
+ * flags as for pic_push_interp, plus PIC_SORT_CELLS.  With FDTD2 and no
+ * current filter the deposit and the E update run as one
+ * pic_deposit_current(PIC_DEPOSIT_CURL_E) call. */
 pic_status pic_step(pic_ctx *ctx, uint32_t flags);
 
 /* Capture nsteps calls of pic_step(flags) into a HIP graph on the context's

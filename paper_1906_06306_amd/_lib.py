@@ -27,6 +27,7 @@ PIC_TWO_HALF_B = 4
 PIC_FUSED = 1
 PIC_SORT_CELLS = 2
 PIC_PUSH_HALF_B = 4
+PIC_DEPOSIT_CURL_E = 8
 PIC_OPT_ACC_WORKING = 1
 PIC_OPT_PERSISTENT = 2
 PIC_OPT_TRACK = 4

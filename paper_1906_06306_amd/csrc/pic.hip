@@ -466,7 +466,7 @@ struct Impl {
         return halfb ? push_with<true, true, Acc>(x) : push_with<true, false, Acc>(x);
     }
 
-    static pic_status deposit(pic_ctx *x, bool unfused_part)
+    static pic_status deposit(pic_ctx *x, bool unfused_part, bool curl_e)
     {
         Params<R> p = params<R>(x);
         dim3 g((unsigned)x->L.pub.tiles_total);
@@ -485,7 +485,10 @@ struct Impl {
             }
             HIP_OK(hipGetLastError());
         }
-        hipLaunchKernelGGL((pic::k_fold<R, D>), g, dim3(256), 0, x->stream, p);
+        if (curl_e)
+            hipLaunchKernelGGL((pic::k_fold<R, D, true>), g, dim3(256), 0, x->stream, p, (R)x->c);
+        else
+            hipLaunchKernelGGL((pic::k_fold<R, D, false>), g, dim3(256), 0, x->stream, p, R(0));
         HIP_OK(hipGetLastError());
         return PIC_OK;
     }
@@ -751,7 +754,7 @@ struct Impl {
 pic_status do_init(pic_ctx *x, const int64_t *counts, const pic_init_data *in) { PIC_DISPATCH(x, init(x, counts, in)); }
 pic_status do_fdtd(pic_ctx *x, int phase) { PIC_DISPATCH(x, fdtd(x, phase)); }
 pic_status do_push(pic_ctx *x, bool fused, bool halfb) { PIC_DISPATCH(x, push(x, fused, halfb)); }
-pic_status do_deposit(pic_ctx *x, bool unfused) { PIC_DISPATCH(x, deposit(x, unfused)); }
+pic_status do_deposit(pic_ctx *x, bool unfused, bool curl_e) { PIC_DISPATCH(x, deposit(x, unfused, curl_e)); }
 pic_status do_migrate(pic_ctx *x, bool out, bool in, bool sort) { PIC_DISPATCH(x, migrate(x, out, in, sort)); }
 pic_status do_diag(pic_ctx *x, pic_diag *o, bool per_box) { PIC_DISPATCH(x, diag(x, o, per_box)); }
 pic_status do_adjoint(pic_ctx *x, void *a, void *b, void *c, void *d) { PIC_DISPATCH(x, adjoint(x, a, b, c, d)); }
@@ -921,15 +924,16 @@ pic_status pic_push_interp(pic_ctx *x, uint32_t flags)
 
 pic_status pic_deposit_current(pic_ctx *x, uint32_t flags)
 {
-    (void)flags;
     if (!x) return fail(PIC_E_ARG, "null context");
+    const bool curl_e = flags & PIC_DEPOSIT_CURL_E;
+    if (curl_e && x->order != 2) return fail(PIC_E_ARG, "PIC_DEPOSIT_CURL_E applies the second-order E update; use pic_fdtd_step with FDTD4");
     if (x->state == 1) {
-        pic_status st = do_deposit(x, true);
+        pic_status st = do_deposit(x, true, curl_e);
         if (st) return st;
         x->state = 3;
         return PIC_OK;
     }
-    if (x->state == 2) return do_deposit(x, false);
+    if (x->state == 2) return do_deposit(x, false, curl_e);
     return fail(PIC_E_STATE, "deposit needs a preceding push");
 }
 
@@ -950,27 +954,35 @@ pic_status pic_sort_migrate(pic_ctx *x, uint32_t flags)
     return PIC_OK;
 }
 
+// deposit (or fold), filter, E += c curl- B - J; with FDTD2 and no filter
+// the fold and the E update are one pass.
+static pic_status current_and_e(pic_ctx *x, uint32_t flags)
+{
+    pic_status st;
+    if (!x->filter_passes && x->order == 2) return pic_deposit_current(x, flags | PIC_DEPOSIT_CURL_E);
+    if ((st = pic_deposit_current(x, flags))) return st;
+    if (x->filter_passes && (st = pic_filter_current(x, x->filter_passes))) return st;
+    return pic_fdtd_step(x, PIC_CURL_E_ADD_J);
+}
+
 pic_status pic_step(pic_ctx *x, uint32_t flags)
 {
     pic_status st;
     if (!x) return fail(PIC_E_ARG, "null context");
     if (x->order == 4) flags &= ~PIC_PUSH_HALF_B;   // the in-LDS half update is second order
+    flags &= ~PIC_DEPOSIT_CURL_E;                    // chosen below
     if (flags & PIC_PUSH_HALF_B) {
         // push_half_b1 happens inside the push on its LDS copy of B; both
         // half updates are then applied to the stored B in one pass
         if ((st = pic_push_interp(x, flags))) return st;
         if ((st = pic_fdtd_step(x, PIC_TWO_HALF_B))) return st;
-        if ((st = pic_deposit_current(x, flags))) return st;
-        if (x->filter_passes && (st = pic_filter_current(x, x->filter_passes))) return st;
-        if ((st = pic_fdtd_step(x, PIC_CURL_E_ADD_J))) return st;
+        if ((st = current_and_e(x, flags))) return st;
         return pic_sort_migrate(x, flags);
     }
     if ((st = pic_fdtd_step(x, PIC_HALF_B))) return st;
     if ((st = pic_push_interp(x, flags))) return st;
     if ((st = pic_fdtd_step(x, PIC_HALF_B))) return st;
-    if ((st = pic_deposit_current(x, flags))) return st;
-    if (x->filter_passes && (st = pic_filter_current(x, x->filter_passes))) return st;
-    if ((st = pic_fdtd_step(x, PIC_CURL_E_ADD_J))) return st;
+    if ((st = current_and_e(x, flags))) return st;
     return pic_sort_migrate(x, flags);
 }
 

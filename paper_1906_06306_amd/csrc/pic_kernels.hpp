@@ -471,6 +471,36 @@ __global__ void __launch_bounds__(1024) k_deposit(Params<R> p)
     for (int k = threadIdx.x; k < 3 * cb.n; k += blockDim.x) blk[k] = (R)sJ[k];
 }
 
+// E += h curl- B at one cell with the second-order backward differences of
+// App. B (periodic inside the box), then E -= j when SUB_J; the tangential
+// E vanishes on a wall plane.  Reads B and only this cell's E.
+template <typename R, int D, bool SUB_J>
+__device__ __forceinline__ void curl_b_update_e(const Params<R> &p, const TileDesc &td, int gx, int gy, int gz,
+                                                int64_t g, R h, const R j[3])
+{
+    const int64_t N = p.cells_total;
+    const int n0 = td.n[0], n1 = td.n[1], n2 = td.n[2];
+    auto at = [&](int x, int y, int z) -> int64_t { return td.cell0 + x + (int64_t)n0 * (y + (int64_t)n1 * z); };
+    const R *Bx = p.B, *By = p.B + N, *Bz = p.B + 2 * N;
+    const int64_t im = at(gx == 0 ? n0 - 1 : gx - 1, gy, gz);
+    const int64_t jm = D > 1 ? at(gx, gy == 0 ? n1 - 1 : gy - 1, gz) : g;
+    const int64_t km = D > 2 ? at(gx, gy, gz == 0 ? n2 - 1 : gz - 1) : g;
+    const R bx = Bx[g], by = By[g], bz = Bz[g];
+    const R cx = (bz - Bz[jm]) - (by - By[km]);
+    const R cy = (bx - Bx[km]) - (bz - Bz[im]);
+    const R cz = (by - By[im]) - (bx - Bx[jm]);
+    R ex = p.E[g] + h * cx, ey = p.E[N + g] + h * cy, ez = p.E[2 * N + g] + h * cz;
+    if constexpr (SUB_J) {
+        ex -= j[0];
+        ey -= j[1];
+        ez -= j[2];
+    }
+    if ((td.walls & 1) && gx == 0) ey = ez = R(0);   // tangential E on the wall plane
+    p.E[g] = ex;
+    p.E[N + g] = ey;
+    p.E[2 * N + g] = ez;
+}
+
 // cur_exchange: J on the lattice = sum of the current blocks (one per
 // species) of the tile and of its neighbours whose halo covers the cell, in
 // a fixed order (species, then neighbour offsets ascending, z major).  A
@@ -478,8 +508,11 @@ __global__ void __launch_bounds__(1024) k_deposit(Params<R> p)
 // covered by its own tile and, for l < 2, the tile below or, for l = T-1,
 // the tile above (edges T >= 4); the up to 2^D loads of a species are
 // issued together, without branches.  Edges of 2 take the general loop.
-template <typename R, int D>
-__global__ void __launch_bounds__(256) k_fold(Params<R> p)
+// With CURL_E the same pass also applies E += h curl- B - J to the cell
+// (push_e and add_cur after the second half update of B), from the folded
+// values still in registers: J is written once and not read back.
+template <typename R, int D, bool CURL_E>
+__global__ void __launch_bounds__(256) k_fold(Params<R> p, R h)
 {
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const TileDesc td = p.tiles[t];
@@ -572,6 +605,7 @@ __global__ void __launch_bounds__(256) k_fold(Params<R> p)
         p.J[g] = acc[0];
         p.J[p.cells_total + g] = acc[1];
         p.J[2 * p.cells_total + g] = acc[2];
+        if constexpr (CURL_E) curl_b_update_e<R, D, true>(p, td, gx, gy, gz, g, h, acc);
     }
 }
 
@@ -667,24 +701,13 @@ __global__ void __launch_bounds__(256) k_field(Params<R> p, R h)
             p.E[N + g] = wall ? R(0) : p.E[N + g] - p.J[N + g];
             p.E[2 * N + g] = wall ? R(0) : p.E[2 * N + g] - p.J[2 * N + g];
         } else {
-            const R *Bx = p.B, *By = p.B + N, *Bz = p.B + 2 * N;
-            const int64_t im = D > 0 ? at(gx == 0 ? n0 - 1 : gx - 1, gy, gz) : g;
-            const int64_t jm = D > 1 ? at(gx, gy == 0 ? n1 - 1 : gy - 1, gz) : g;
-            const int64_t km = D > 2 ? at(gx, gy, gz == 0 ? n2 - 1 : gz - 1) : g;
-            const R bx = Bx[g], by = By[g], bz = Bz[g];
-            const R cx = (bz - Bz[jm]) - (by - By[km]);
-            const R cy = (bx - Bx[km]) - (bz - Bz[im]);
-            const R cz = (by - By[im]) - (bx - Bx[jm]);
-            R ex = p.E[g] + h * cx, ey = p.E[N + g] + h * cy, ez = p.E[2 * N + g] + h * cz;
+            R j[3] = {0, 0, 0};
             if constexpr (PHASE == 3) {
-                ex -= p.J[g];
-                ey -= p.J[N + g];
-                ez -= p.J[2 * N + g];
+                j[0] = p.J[g];
+                j[1] = p.J[N + g];
+                j[2] = p.J[2 * N + g];
             }
-            if ((td.walls & 1) && gx == 0) ey = ez = R(0);   // tangential E on the wall plane
-            p.E[g] = ex;
-            p.E[N + g] = ey;
-            p.E[2 * N + g] = ez;
+            curl_b_update_e<R, D, PHASE == 3>(p, td, gx, gy, gz, g, h, j);
         }
     }
 }

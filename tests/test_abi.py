@@ -32,6 +32,17 @@ def test_exports_match_header(lib):
     assert set(names) == set(lib.EXPORTS)
 
 
+def test_constants_match_header(lib):
+    src = open(os.path.join(ROOT, "include", "pic.h")).read()
+    seen = 0
+    for name, val in re.findall(r"^#define (PIC_\w+) (\(1 << \d+\)|\d+)u?\b", src, re.M):
+        v = 1 << int(val[6:-1]) if val.startswith("(") else int(val)
+        if hasattr(lib, name):
+            assert getattr(lib, name) == v, name
+            seen += 1
+    assert seen >= 20 and lib.PIC_DEPOSIT_CURL_E == 8
+
+
 def make_cfg(lib, D=2, n=(64, 64, 1), T=(16, 16, 1), prec=0, cfl=0.45, ns=2):
     cells = np.array([list(n)], dtype=np.int32)
     q = np.array([[-1e-3, 1e-3][:ns]], dtype=np.float64)

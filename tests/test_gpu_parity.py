@@ -169,6 +169,63 @@ def test_fused_step_matches_oracle_and_unfused(D, n, T, ppc, prec, half_b_in_pus
     ref.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("walls", [False, True])
+@pytest.mark.parametrize("D,n,T,ppc", CASES)
+def test_step_with_fold_and_e_in_one_pass_matches_separate_calls(D, n, T, ppc, prec, walls):
+    """pic_step after a fused push folds the current blocks and applies
+    E += c curl- B - J in one pass; the separate calls (fold, then the E
+    update) compute the same values: bit for bit in FP32, whose current sums
+    are exact, and to rounding in FP64 (LDS atomics add in no fixed order).
+    Four steps, with and without conducting walls."""
+    from paper_1906_06306_amd import _lib as L
+    plasma = synth.small_random(D, n, ppc, theta=2.0 if walls else 0.3, seed=71 + D,
+                                field_amp=0.05, q=0.01)
+    a = make_sim(plasma, T, prec, walls=walls, capacity_factor=3.0)
+    b = make_sim(plasma, T, prec, walls=walls, capacity_factor=3.0)
+    for _ in range(4):
+        a.step(1, fused=True, half_b_in_push=True)
+        b.push(fused=True, half_b=True)
+        b.fdtd(L.PIC_TWO_HALF_B)
+        b.deposit()
+        b.fdtd(L.PIC_CURL_E_ADD_J)
+        b.sort_migrate()
+    assert a.error() == 0 and b.error() == 0
+    for x, y in zip(a.fields_host(0), b.fields_host(0)):
+        if prec == "fp32":
+            assert np.array_equal(x, y)
+        else:
+            assert rel(x, y) < 1e-13
+    for s in range(2):
+        pa, pb = a.particles_host(0, s), b.particles_host(0, s)
+        assert np.array_equal(pa[0], pb[0])
+        if prec == "fp32":
+            assert np.array_equal(pa[1], pb[1]) and np.array_equal(pa[2], pb[2])
+        else:
+            assert np.abs(pa[1] - pb[1]).max() < 1e-12 and np.abs(pa[2] - pb[2]).max() < 1e-12
+    a.close()
+    b.close()
+
+
+def test_fold_with_e_update_is_refused_under_fdtd4():
+    """PIC_DEPOSIT_CURL_E carries the second-order E update: with FDTD4 the
+    call fails with PIC_E_ARG and leaves the step where it was."""
+    from paper_1906_06306_amd import _lib as L
+    plasma = synth.small_random(2, (32, 32), 2, seed=5)
+    sim = make_sim(plasma, (8, 8), "fp64", fdtd_order=4)
+    sim.fdtd(L.PIC_HALF_B)
+    sim.push(fused=True)
+    sim.fdtd(L.PIC_HALF_B)
+    with pytest.raises(L.PicError) as e:
+        L.check(L.lib().pic_deposit_current(sim.ctx, L.PIC_DEPOSIT_CURL_E))
+    assert e.value.code == L.PIC_E_ARG
+    sim.deposit()
+    sim.fdtd(L.PIC_CURL_E_ADD_J)
+    sim.sort_migrate()
+    assert sim.error() == 0
+    sim.close()
+
+
 def test_fp32_runs_are_bit_reproducible():
     """The FP32 push adds the current in 64-bit fixed point (exact integer
     adds), so the state after several steps does not depend on the order in
