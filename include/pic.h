@@ -12,9 +12,11 @@
  *                                      cur_exchange            App. D
  *   pic_fdtd_step(PIC_CURL_E_ADD_J)    push_e + add_cur        Eq. (fdE)
  *   pic_sort_migrate(...)              particle communication rows
- * pic_step() enqueues exactly that sequence; with PIC_PUSH_HALF_B the
- * first half update runs inside the push (on its LDS copy of B) and both
- * halves are applied to the stored B by one PIC_TWO_HALF_B pass.
+ * pic_step() enqueues that sequence; with PIC_PUSH_HALF_B the first half
+ * update runs inside the push (on its LDS copy of B) and both halves are
+ * applied to the stored B by one PIC_TWO_HALF_B pass, and with FDTD2 and no
+ * current filter the last two rows before the migration are one
+ * pic_deposit_current(PIC_DEPOSIT_CURL_E) pass.
  *
  * Units (App. A): dx = dt = 1, Courant number c = cfl; E, B, J in code
  * units; four-velocities u in units of the speed of light.
