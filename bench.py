@@ -669,8 +669,12 @@ def main():
     }
     if r64 is not None:
         v64 = n_p * args.steps / r64["seconds"]
+        pb64 = push_bytes(D, 8, n_p, n_c)
+        a64 = pb64 / (r64["push_ms"] * 1e-3) / 1e9
         out["fp64"] = {"value": v64, "ms_per_step": r64["seconds"] / args.steps * 1e3,
                        "push_ms": r64["push_ms"], "speedup_fp32_over_fp64": value / v64,
+                       "push_roofline": {"bound": "hbm", "achieved": a64, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                         "frac": a64 / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": pb64},
                        "tile": tile64, "block": blk64, "autotune_ms_per_step": tune64,
                        "gauss_max": r64["diag"]["gauss_max"], "continuity_max": r64["diag"]["continuity_max"],
                        "status": r64["diag"]["status"],

@@ -35,3 +35,5 @@ def test_algorithmic_bytes_of_the_turbulence_step():
     assert abs(bench.algorithmic_bytes(2, 4, n_p, n_c) / 1e9 - 1.4177) < 1e-3
     # the push alone: particles plus E, B read and J written (9 words per cell)
     assert bench.push_bytes(2, 4, n_p, n_c) == n_p * 40 + n_c * 36
+    # FP64 words double every term
+    assert bench.push_bytes(2, 8, n_p, n_c) == 2 * bench.push_bytes(2, 4, n_p, n_c)
