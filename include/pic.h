@@ -268,7 +268,8 @@ pic_status pic_fdtd_step(pic_ctx *ctx, int32_t phase);
  * the old ones in the xold region, for pic_deposit_current and
  * pic_sort_migrate.  One work-group handles one (tile, species) segment;
  * the segments are visited in decreasing particle count (re-sorted on the
- * device at every call).  With PIC_FUSED the same work-group also deposits
+ * device at every 8th push, at the first push after init or an injection,
+ * and at every captured push; the order does not change the results).  With PIC_FUSED the same work-group also deposits
  * the ZigZag current of its particles into the segment's current block
  * (App. D) and compacts the particles that stay, moving leavers to the
  * segment's outbox (the "tag outflowing / pack" rows of Table 1). */

@@ -32,6 +32,12 @@ namespace {
 // byte offsets from the segment's base, 8 * 2^28 bytes at FP64
 constexpr int64_t MAX_SLOTS = int64_t(1) << 28;
 
+// the segments' visiting order (largest first) only balances the push: any
+// permutation gives the same results, and counts change by a few percent a
+// step, so it is recomputed every ORDER_EVERY pushes, at the first push after
+// init or an injection, and at every push captured into a graph
+constexpr int ORDER_EVERY = 8;
+
 thread_local std::string g_last_error;
 
 pic_status fail(pic_status code, const char *fmt, ...)
@@ -275,6 +281,8 @@ struct pic_ctx {
     int filter_passes;  // binomial passes pic_step applies to J
     int order;          // FDTD order: 2 (App. B) or 4 (FDTD4)
     int64_t steps;      // completed steps
+    int order_age;      // pushes since the visiting order was recomputed
+    bool capturing;     // pic_graph_capture is recording steps
     int64_t diag_step;  // steps at the last diagnostics call, or -1
     int n_cu;           // compute units of the device
     hipGraphExec_t graph;   // captured steps, or null
@@ -408,8 +416,12 @@ struct Impl {
         size_t lds = push_lds(x, FUSED, sizeof(A));
         dim3 b(x->block);
         const int64_t items = x->L.pub.tiles_total * x->ns;
-        pic_status st0 = order_segments(x, p);
-        if (st0) return st0;
+        if (x->capturing || x->order_age >= ORDER_EVERY) {
+            pic_status st0 = order_segments(x, p);
+            if (st0) return st0;
+            x->order_age = 0;
+        }
+        ++x->order_age;
         if (x->persistent) {
             auto kern = pic::k_push_persistent<R, D, FUSED, HALFB, A, PUSH_UNROLL, TC, WALLS, PUSHER>;
             pic_status st = set_lds(kern, lds);
@@ -853,6 +865,8 @@ pic_status pic_init_tiles(const pic_config *cfg, const int64_t *counts, void *wo
     x->filter_passes = cfg->filter_passes;
     x->order = cfg->fdtd_order == 4 ? 4 : 2;
     x->steps = 0;
+    x->order_age = ORDER_EVERY;
+    x->capturing = false;
     x->diag_step = -1;
     for (int b = 0; cfg->box_walls && b < cfg->n_boxes; ++b) x->walls = x->walls || (cfg->box_walls[b] & PIC_WALL_X);
     x->graph = nullptr;
@@ -995,6 +1009,7 @@ pic_status pic_inject(pic_ctx *x, int32_t box, int32_t species, int64_t count, c
         return fail(PIC_E_ARG, "a batch holds at most %lld particles (pic_config.inject_max)", (long long)x->L.max_count);
     if (count == 0) return PIC_OK;
     if (!pos || !u) return fail(PIC_E_ARG, "pos and u are required");
+    x->order_age = ORDER_EVERY;   // counts changed: re-sort at the next push
     return do_inject(x, box, species, count, pos, u);
 }
 
@@ -1022,7 +1037,9 @@ pic_status pic_graph_capture(pic_ctx *x, int32_t nsteps, uint32_t flags)
     HIP_OK(hipStreamSynchronize(x->stream));
     const int64_t steps_before = x->steps;   // captured steps do not run now
     HIP_OK(hipStreamBeginCapture(x->stream, hipStreamCaptureModeThreadLocal));
+    x->capturing = true;
     for (int k = 0; k < nsteps && !st; ++k) st = pic_step(x, flags);
+    x->capturing = false;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(x->stream, &g);
     x->steps = steps_before;
