@@ -140,19 +140,19 @@ def run_gpu(plasma, args, precision, steps, warmup, tile, block=256, profile_onl
             L.check(lib.pic_fdtd_step(ctx, L.PIC_HALF_B))
         if ev is not None:
             ev[0].record(stream)
-        L.check(lib.pic_push_interp(ctx, flags))
+        L.check(lib.pic_push_interp(ctx, L.PIC_ALL_SPECIES, flags))
         if ev is not None:
             ev[1].record(stream)
         L.check(lib.pic_fdtd_step(ctx, L.PIC_TWO_HALF_B if halfb else L.PIC_HALF_B))
         if fold_e:
             # the fold and E += c curl B - J in one pass
-            L.check(lib.pic_deposit_current(ctx, flags | L.PIC_DEPOSIT_CURL_E))
+            L.check(lib.pic_deposit_current(ctx, L.PIC_ALL_SPECIES, flags | L.PIC_DEPOSIT_CURL_E))
         else:
-            L.check(lib.pic_deposit_current(ctx, flags))
+            L.check(lib.pic_deposit_current(ctx, L.PIC_ALL_SPECIES, flags))
             if args.filter_passes:
                 L.check(lib.pic_filter_current(ctx, args.filter_passes))
             L.check(lib.pic_fdtd_step(ctx, L.PIC_CURL_E_ADD_J))
-        L.check(lib.pic_sort_migrate(ctx, 0))
+        L.check(lib.pic_sort_migrate(ctx, 0, None, None, 0))
 
     if profile_only:
         for _ in range(steps):
@@ -183,32 +183,123 @@ def run_gpu(plasma, args, precision, steps, warmup, tile, block=256, profile_onl
     return dict(seconds=dt, push_ms=push_ms, diag=diag)
 
 
-def cpu_oracle_rate(plasma, steps):
-    """The FP64 oracle, as it stands, on full steps of the same workload;
-    also returns E, B, J after its first step (the reference the GPU paths'
-    one-step error is stated against)."""
+def host_threads() -> int:
+    """Host threads the all-thread oracle uses: the CPUs this process may
+    run on, at most 16 (one GPU's share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_oracle_rate(plasma, steps, threads=1):
+    """The FP64 oracle, as it stands, on full steps of the same workload, on
+    one host thread (orc_step) or on `threads` (orc_step_threads: per-thread
+    particle ranges and currents summed in thread order); also returns E, B,
+    J after its first step (the reference the GPU paths' one-step error is
+    stated against)."""
     import oracle
     st = oracle.State(plasma)
     t0 = time.perf_counter()
-    st.step(1)
+    st.step(1, threads=threads)
     t1 = time.perf_counter()
     first = (st.E.copy(), st.B.copy(), st.J.copy())
     t2 = time.perf_counter()
-    st.step(steps - 1)
+    st.step(steps - 1, threads=threads)
     dt = (t1 - t0) + (time.perf_counter() - t2)
     return plasma.nparticles * steps / dt, dt, first
 
 
+def common_state_error(plasma, precision, tile, block):
+    """One GPU step from the GPU's own binned state against the oracle's
+    step from that state widened to FP64 (whole lattice).  Where the two put
+    a particle's end point in different cells (an end point within rounding
+    of a face), the oracle deposits from the kernel's end point, so both take
+    that integer decision in the kernel's precision; those particles are
+    counted and must all be flagged near a face."""
+    import torch
+    import oracle
+    from oracle import tiles
+    from paper_1906_06306_amd import _lib as L
+    from paper_1906_06306_amd.sim import PicSim
+    T = (tile, tile, 1)
+    dims = tuple(plasma.n)
+    n0 = dims[0]
+    sim = PicSim(plasma, tile=(tile, tile), precision=precision, block=block, capacity_factor=3.0,
+                 options=L.PIC_OPT_TRACK)
+
+    def slots(s):
+        _, _, _, off, cnt = sim.particle_views()
+        off, cnt = off.cpu().numpy(), cnt.cpu().numpy()
+        return np.concatenate([np.arange(off[t, s], off[t, s] + cnt[t, s]) for t in range(off.shape[0])])
+
+    st = oracle.State(plasma)
+    E0, B0, _ = sim.fields_host(0)
+    st.E[:], st.B[:] = E0, B0
+    sl0 = []
+    for s in range(2):
+        tid, xl, u = sim.particles_host(0, s)
+        st.x[s] = np.ascontiguousarray(tiles.to_global(tid, xl, dims, T, 2))
+        st.u[s] = np.ascontiguousarray(u.astype(np.float64))
+        sl0.append(slots(s))
+    sim.step(1, fused=True, half_b_in_push=True)
+    total, flagged = sim.sort_migrate(flagged_capacity=1 << 22)
+    flagged = np.sort(flagged)
+    ids = sim.ids_host()
+    ends = st.push_particles()
+    realigned = unflagged = 0
+    for s in range(2):
+        tid1, xl1, _ = sim.particles_host(0, s)
+        sl1 = slots(s)
+        inv = np.full(ids.size, -1, dtype=np.int64)
+        inv[sl0[s]] = np.arange(sl0[s].size)
+        k = inv[ids[sl1]]
+        xg = tiles.to_global(tid1, xl1, dims, T, 2)
+        xk = xg + n0 * np.round((ends[s][:, k] - xg) / n0)
+        diff = (np.floor(xk) != np.floor(ends[s][:, k])).any(axis=0)
+        realigned += int(diff.sum())
+        unflagged += int((~np.isin(sl1[diff], flagged)).sum())
+        ends[s][:, k[diff]] = xk[:, diff]
+    st.finish_step(ends)
+    out = {}
+    for name, g, r in zip(("E", "B", "J"), sim.fields_host(0), (st.E, st.B, st.J)):
+        out[name] = float(np.linalg.norm(g - r) / np.linalg.norm(r))
+    out["end_cells_taken_from_kernel"] = realigned
+    out["of_them_unflagged"] = unflagged
+    out["near_face_flagged"] = int(total)
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
 def one_step_error(plasma, precision, tile, ref):
     """Relative L2 of E, B, J after one GPU step from the input state
-    against the oracle's first step (input rounding included)."""
+    against the oracle's first step (input rounding included), and the
+    particles flagged near a face before and after it (the ones whose cell,
+    and so whose ZigZag relay point, rounding can change)."""
     import torch
     from paper_1906_06306_amd.sim import PicSim
     sim = PicSim(plasma, tile=(tile, tile), precision=precision, capacity_factor=3.0)
+    nf0 = sim.diagnostics()["near_face"]
     sim.step(1, fused=True, half_b_in_push=True)
     out = {}
     for name, g, r in zip(("E", "B", "J"), sim.fields_host(0), ref):
         out[name] = float(np.linalg.norm(g - r) / np.linalg.norm(r))
+    out["near_face_flagged_at_input"] = int(nf0)
+    out["near_face_flagged_after_step"] = int(sim.diagnostics()["near_face"])
     sim.close()
     del sim
     torch.cuda.empty_cache()
@@ -368,11 +459,11 @@ def bench_shock(args):
         t1 = time.perf_counter()
         for k in range(args.steps):
             evs[k][0].record(stream)
-            L.check(lib.pic_push_interp(sim.ctx, flags))
+            L.check(lib.pic_push_interp(sim.ctx, L.PIC_ALL_SPECIES, flags))
             evs[k][1].record(stream)
             L.check(lib.pic_fdtd_step(sim.ctx, L.PIC_TWO_HALF_B))
-            L.check(lib.pic_deposit_current(sim.ctx, flags | L.PIC_DEPOSIT_CURL_E))
-            L.check(lib.pic_sort_migrate(sim.ctx, 0))
+            L.check(lib.pic_deposit_current(sim.ctx, L.PIC_ALL_SPECIES, flags | L.PIC_DEPOSIT_CURL_E))
+            L.check(lib.pic_sort_migrate(sim.ctx, 0, None, None, 0))
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
         push_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
@@ -615,16 +706,26 @@ def main():
         log(f"fp64 run, tile {tile64}, block {blk64}")
         r64 = run_gpu(plasma, args, "fp64", args.steps, args.warmup, tile64, blk64)
     cpu = None
-    err32 = err64 = None
+    err32 = err64 = cs32 = cs64 = None
     if not args.no_cpu:
-        log(f"cpu oracle: {args.cpu_steps} full steps")
-        rate, sec, first = cpu_oracle_rate(plasma, args.cpu_steps)
-        cpu = {"value": rate, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+        nth = host_threads()
+        log(f"cpu oracle: {args.cpu_steps} full steps on 1 thread")
+        rate1, sec1, first = cpu_oracle_rate(plasma, args.cpu_steps)
+        log(f"cpu oracle: {args.cpu_steps} full steps on {nth} threads")
+        rate_n, sec_n, _ = cpu_oracle_rate(plasma, args.cpu_steps, threads=nth)
+        cpu = {"value": rate_n, "unit": "particle-steps/s", "cores": nth, "kind": "oracle",
                "sample": f"{args.cpu_steps} full steps of the same {args.n}^2 workload ({n_p} particles), "
-                         f"single-threaded FP64 C oracle, {sec:.1f} s"}
+                         f"FP64 C oracle on {nth} host threads (per-thread particle ranges and currents, "
+                         f"summed in thread order), {sec_n:.1f} s",
+               "single_thread": {"value": rate1, "cores": 1, "seconds": sec1},
+               "os_cpu_count": os.cpu_count(), "cpu_model": cpu_model()}
         log("one-step error of the GPU paths against the oracle")
         err32 = one_step_error(plasma, "fp32", tile32, first)
         err64 = one_step_error(plasma, "fp64", tile64 if r64 is not None else tile32, first)
+        log("one-step error from the GPU's own state (common state)")
+        cs32 = common_state_error(plasma, "fp32", tile32, blk32)
+        if r64 is not None:
+            cs64 = common_state_error(plasma, "fp64", tile64, blk64)
     for name, r in (("FP32", r32), ("FP64", r64)):
         if r is not None and r["diag"]["status"] != 0:
             # a latched overflow or numerical error: the state, and so the
@@ -657,6 +758,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": MEASURED_PUSH_TRAFFIC.get((kernel_source_hash(), "fp32", tile32, args.n, args.ppc)),
+                     "traffic_source": "stored: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE of this kernel on this "
+                                       "workload, scaled by a plain copy, averaged over a whole run, for the kernel "
+                                       "sources with the hash kernel_sources (null for other sources)",
                      "kernel": "k_push<float,2,fused>", "push_ms": r32["push_ms"],
                      "algorithmic_bytes_per_launch": pb, "kernel_sources": kernel_source_hash(),
                      "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
@@ -666,6 +770,7 @@ def main():
                                                          "max_segment_fill", "status")},
         "cpu_baseline": cpu,
         "fp32_vs_oracle_1step_rel_l2": err32,
+        "fp32_vs_oracle_common_state_rel_l2": cs32,
     }
     if r64 is not None:
         v64 = n_p * args.steps / r64["seconds"]
@@ -678,7 +783,8 @@ def main():
                        "tile": tile64, "block": blk64, "autotune_ms_per_step": tune64,
                        "gauss_max": r64["diag"]["gauss_max"], "continuity_max": r64["diag"]["continuity_max"],
                        "status": r64["diag"]["status"],
-                       "vs_oracle_1step_rel_l2": err64}
+                       "vs_oracle_1step_rel_l2": err64,
+                       "vs_oracle_common_state_rel_l2": cs64}
     print(json.dumps(out), flush=True)
 
 

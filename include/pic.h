@@ -100,6 +100,11 @@ typedef int32_t pic_status;
                                PIC_CURL_E_ADD_J) in the fold's pass, from the
                                folded J; FDTD2 only                         */
 
+/* species_mask of pic_push_interp / pic_deposit_current: bit s selects
+ * species s (Table 1 runs interp_em, push and comp_curr once per particle
+ * container); PIC_ALL_SPECIES selects every species. */
+#define PIC_ALL_SPECIES 0xffffffffu
+
 typedef struct {
     int32_t dim;          /* spatial dimensions D in {1,2,3}                 */
     int32_t precision;    /* PIC_FP32 or PIC_FP64                           */
@@ -196,7 +201,9 @@ typedef struct {
     uint64_t off_seg_capacity;              /* int32 [tiles][species]          */
     uint64_t off_seg_count;                 /* int32 [tiles][species]          */
     uint64_t off_error;                     /* int32 latched device error bits */
-    uint64_t off_flags;                     /* int64 near-face counter          */
+    uint64_t off_flags;                     /* int32 [tiles][species] particles
+                                               of each segment flagged near a
+                                               cell face (see pic_diag)        */
     uint64_t off_ids;                       /* int32 [capacity_total] origin of
                                                each particle (PIC_OPT_TRACK)   */
     int64_t cells_total;
@@ -227,8 +234,17 @@ typedef struct {
     double divb_max;         /* max |div+ B| on cell centres                 */
     double charge_total;     /* sum rho                                      */
     int64_t particles;       /* particles stored                            */
-    int64_t near_face;       /* particles flagged within 1 ulp of a cell face
-                                by the last init or sort                    */
+    int64_t near_face;       /* particles flagged near a cell face: a
+                                stored tile-local coordinate x lies within
+                                2 ulps of the storage precision at the tile
+                                half-width, |x - rint(x)| <= 2 ulp(T_d/2),
+                                of an integer.  Every particle within 1 ulp
+                                of a face is among them, and so is every
+                                particle whose cell an FP32 step can put on
+                                the other side of a face than the FP64 step
+                                from the same input.  Counted over the
+                                state after the last init, injection, push
+                                or cell sort.                               */
     int32_t error_bits;      /* latched device errors (then cleared)         */
     int32_t reserved;
     double continuity_max;   /* max |rho^{n+1} - rho^n + div- J| on nodes (App.
@@ -261,9 +277,16 @@ pic_status pic_init_tiles(const pic_config *cfg, const int64_t *counts, void *wo
  * PIC_ADD_J, PIC_CURL_E_ADD_J or PIC_TWO_HALF_B. */
 pic_status pic_fdtd_step(pic_ctx *ctx, int32_t phase);
 
-/* interp_em + push for every particle: linear interpolation of each E and B
+/* interp_em + push for every particle of the species in species_mask:
+ * linear interpolation of each E and B
  * component from its own staggered lattice (Sect. 2.3.2), relativistic
  * Boris update of u (App. C), position advance x += c u/gamma (Eq. fdX).
+ * One step may push its species in several calls with disjoint masks (all
+ * with the same PIC_FUSED setting) before its deposit and migration; a
+ * species pushed twice in a step, an empty mask or a bit beyond n_species
+ * is rejected (PIC_E_STATE, PIC_E_ARG), and with PIC_OPT_TRACK the mask
+ * must cover every species.  The push also counts, per segment, the
+ * particles it leaves near a cell face (pic_diag.near_face).
  * Without PIC_FUSED the new positions are stored in place unrebased and
  * the old ones in the xold region, for pic_deposit_current and
  * pic_sort_migrate.  One work-group handles one (tile, species) segment;
@@ -273,28 +296,50 @@ pic_status pic_fdtd_step(pic_ctx *ctx, int32_t phase);
  * the ZigZag current of its particles into the segment's current block
  * (App. D) and compacts the particles that stay, moving leavers to the
  * segment's outbox (the "tag outflowing / pack" rows of Table 1). */
-pic_status pic_push_interp(pic_ctx *ctx, uint32_t flags);
+pic_status pic_push_interp(pic_ctx *ctx, uint32_t species_mask, uint32_t flags);
 
-/* comp_curr + clear_vir_cur + cur_exchange: after an unfused push, ZigZag
+/* comp_curr + clear_vir_cur + cur_exchange for the species in species_mask
+ * (each pushed in this step): after an unfused push, ZigZag
  * deposit from (xold, x) into per-segment current blocks; in both modes, sum
- * the blocks (every species of the tile plus the halos of its neighbours)
- * into J on the lattice, in a fixed order.  With PIC_DEPOSIT_CURL_E the same
+ * the blocks (every selected species of the tile plus the halos of its
+ * neighbours) into J on the lattice, in a fixed order, so J is the current
+ * of the selected species only.  One call per step.  With PIC_DEPOSIT_CURL_E the same
  * pass then updates E at each cell as pic_fdtd_step(PIC_CURL_E_ADD_J) would
  * (Eq. (fdE), same arithmetic), so the step saves that launch and the re-read
  * of J; B must already hold B^{n+1/2}.  PIC_E_ARG with the flag under FDTD4,
- * PIC_E_STATE without a preceding push. */
-pic_status pic_deposit_current(pic_ctx *ctx, uint32_t flags);
+ * PIC_E_STATE without a preceding push of every selected species. */
+pic_status pic_deposit_current(pic_ctx *ctx, uint32_t species_mask, uint32_t flags);
 
 /* Particle communication rows of Table 1: after an unfused push, move the
  * particles that left each tile out (stable compaction); then every tile
  * appends the arrivals from its neighbours (directions in increasing code
  * sum (delta_d+1) 3^d, each in the sender's order) with positions rebased
  * by -delta T (exact).  PIC_SORT_CELLS then sorts every tile segment
- * stably by cell index (x fastest) and recounts near-face particles. */
-pic_status pic_sort_migrate(pic_ctx *ctx, uint32_t flags);
+ * stably by cell index (x fastest) and recounts near-face particles.
+ *
+ * Optional outputs (device buffers the caller owns, or NULL; written on the
+ * context's stream, nothing synchronises):
+ *   migration_counts  int32 [tiles_total][n_species][3^dim]: entry (t, s, k)
+ *                     is the number of particles of species s that were in
+ *                     tile t before the step and are in the neighbour at
+ *                     offset delta (k = sum_d (delta_d + 1) 3^d, tiles of a
+ *                     box periodic) after it; the centre code counts the
+ *                     particles that stayed.  Needs a preceding push
+ *                     (PIC_E_STATE otherwise); species not pushed in the
+ *                     step count as staying.
+ *   flagged           int64 [flagged_capacity + 1]: flagged[0] receives the
+ *                     number of particles flagged near a cell face after the
+ *                     call (the rule of pic_diag.near_face), flagged[1..]
+ *                     the particle slots (element index into the particle
+ *                     planes) of the first min(that number,
+ *                     flagged_capacity) of them in increasing slot order.
+ *                     Costs one extra pass over the positions.
+ * PIC_E_ARG if flagged_capacity < 0. */
+pic_status pic_sort_migrate(pic_ctx *ctx, uint32_t flags, int32_t *migration_counts, int64_t *flagged,
+                            int64_t flagged_capacity);
 
-/* One full time step in Table-1 order (see the top of this header);
- * flags as for pic_push_interp, plus PIC_SORT_CELLS.  With FDTD2 and no
+/* One full time step in Table-1 order (see the top of this header), every
+ * species; flags as for pic_push_interp, plus PIC_SORT_CELLS.  With FDTD2 and no
  * current filter the deposit and the E update run as one
  * pic_deposit_current(PIC_DEPOSIT_CURL_E) call. */
 pic_status pic_step(pic_ctx *ctx, uint32_t flags);
@@ -338,7 +383,7 @@ pic_status pic_error(pic_ctx *ctx);
 pic_status pic_diagnostics(pic_ctx *ctx, pic_diag *out);
 
 /* The same diagnostics per box: out is a host array of n_boxes entries
- * (near_face and error_bits are the context's, repeated in every entry). */
+ * (error_bits is the context's, repeated in every entry). */
 pic_status pic_diagnostics_boxes(pic_ctx *ctx, pic_diag *out);
 
 /* Reverse mode.  The adjoint of one step maps the sensitivities of a loss

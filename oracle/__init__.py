@@ -29,7 +29,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-                               "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
+                               "-shared", "-Wall", "-pthread", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -68,6 +68,7 @@ def lib():
             "orc_field_energy": (Dbl, [P, P, P]),
             "orc_kinetic_energy": (Dbl, [I64, Dbl, Dbl, P]),
             "orc_step_adjoint": (I, [I, P, Dbl, I, P, P, P, P, P, P, P, P, P, P, P]),
+            "orc_step_threads": (I, [I, P, Dbl, I, P, P, P, P, P, P, P, P, I]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -228,12 +229,18 @@ class State:
         self.m = [float(s.m) for s in plasma.species]
 
     def step(self, nsteps: int = 1, walls: bool = False, pusher: int = 0, filter_passes: int = 0,
-             fdtd_order: int = 2):
+             fdtd_order: int = 2, threads: int = 1):
         """nsteps full steps; walls=True: conducting, reflecting walls at
         x = 0 and x = n0 (y, z periodic), else periodic everywhere; pusher
         0 Boris, 1 Vay, 2 Higuera-Cary; filter_passes binomial passes on J;
-        fdtd_order 2 or 4."""
-        if pusher or filter_passes or fdtd_order != 2:
+        fdtd_order 2 or 4.  threads > 1 (periodic Boris/FDTD2 step only):
+        the particle rows on that many host threads, per-thread currents
+        summed in thread order."""
+        if threads > 1:
+            if walls or pusher or filter_passes or fdtd_order != 2:
+                raise ValueError("the threaded step covers the periodic Boris/FDTD2 step")
+            fn = lambda *a: lib().orc_step_threads(*a, int(threads))
+        elif pusher or filter_passes or fdtd_order != 2:
             extra = (int(walls), int(pusher), int(filter_passes), int(fdtd_order))
             fn = lambda *a: lib().orc_step_opts(*a, *extra)
         else:
@@ -251,6 +258,40 @@ class State:
                                 _p(q), _p(s), _p(self.E), _p(self.B), _p(self.J))
             if rc != 0:
                 raise MemoryError("oracle step could not allocate scratch")
+
+    def push_particles(self):
+        """First half of one periodic Boris/FDTD2 step, with the routines
+        and in the order of orc_step: push_half_b1, then interp_em and push
+        of every species.  Returns the unwrapped end points x^{n+1} (one
+        (D, np) array per species); finish_step completes the step."""
+        self._x1 = [x.copy() for x in self.x]
+        self._disp = []
+        advance_b(self.D, self.n, 0.5 * self.c, self.E, self.B)
+        ends = []
+        for s in range(len(self.x)):
+            Ep, Bp = interp(self.D, self.n, self.E, self.B, self.x[s])
+            boris(self.c, self.s[s], Ep, Bp, self.u[s])
+            x2 = np.ascontiguousarray(self.x[s].copy())
+            self._disp.append(move(self.D, self.c, self.u[s], x2))
+            ends.append(x2)
+        return ends
+
+    def finish_step(self, ends):
+        """Second half of the step begun by push_particles: push_half_b2,
+        push_e, comp_curr from the start points to `ends` (the end points
+        push_particles returned, or the same points with some replaced by a
+        caller that takes a cell decision in another precision), the wrap
+        and add_cur."""
+        advance_b(self.D, self.n, 0.5 * self.c, self.E, self.B)
+        advance_e(self.D, self.n, self.c, self.B, self.E)
+        self.J[:] = 0.0
+        for s in range(len(self.x)):
+            x2 = np.ascontiguousarray(ends[s], dtype=np.float64)
+            zigzag(self.D, self.n, self.q[s], self._x1[s], x2, self._disp[s], self.J)
+            wrap(self.D, self.n, x2)
+            self.x[s] = x2
+        add_current(self.n, self.J, self.E)
+        del self._x1, self._disp
 
     def append(self, species: int, x, u):
         """Add particles (global x (D, k), u (3, k)) after the existing ones:

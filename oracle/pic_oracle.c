@@ -1207,3 +1207,146 @@ int orc_step_adjoint(int D, const int n[3], double c, int nspecies, const int64_
     free(lJ);
     return 0;
 }
+
+/* ====================================================================== */
+/* The same step on several host threads, for the CPU baseline: each thread
+ * takes a contiguous range of every species' particles through interp_em,
+ * push, comp_curr and the wrap with the single-thread routines above (on a
+ * private copy of its range) and deposits into a private current array; the
+ * field rows stay single-threaded, and the per-thread currents are summed
+ * cell by cell in thread order, so a run is reproducible for a given thread
+ * count.  Particles and fields equal orc_step's; J (and so E) only differ
+ * by the order of the current sums.                                       */
+
+#include <pthread.h>
+
+struct orc_range {
+    int D, ns;
+    const int *n;
+    double c;
+    const int64_t *n_per;
+    double **x, **u;
+    const double *q, *sgn, *E, *B;
+    double *J;                 /* this thread's current, 3 N */
+    int t, nthreads;
+    int ok;
+};
+
+static void part_range(int64_t np, int t, int nt, int64_t *a, int64_t *b)
+{
+    *a = np * t / nt;
+    *b = np * (t + 1) / nt;
+}
+
+static void *orc_range_worker(void *arg)
+{
+    struct orc_range *r = (struct orc_range *)arg;
+    int D = r->D;
+    r->ok = 1;
+    for (int s = 0; s < r->ns; ++s) {
+        int64_t np = r->n_per[s], a, b;
+        part_range(np, r->t, r->nthreads, &a, &b);
+        int64_t m = b - a;
+        if (m <= 0) continue;
+        double *xs = malloc(sizeof(double) * (size_t)(D * m));
+        double *xo = malloc(sizeof(double) * (size_t)(D * m));
+        double *us = malloc(sizeof(double) * (size_t)(3 * m));
+        double *fp = malloc(sizeof(double) * (size_t)(6 * m));
+        double *dp = malloc(sizeof(double) * (size_t)(3 * m));
+        if (!xs || !xo || !us || !fp || !dp) {
+            r->ok = 0;
+        } else {
+            for (int d = 0; d < D; ++d) memcpy(xs + d * m, r->x[s] + d * np + a, sizeof(double) * (size_t)m);
+            for (int i = 0; i < 3; ++i) memcpy(us + i * m, r->u[s] + i * np + a, sizeof(double) * (size_t)m);
+            memcpy(xo, xs, sizeof(double) * (size_t)(D * m));
+            orc_interp(D, r->n, r->E, r->B, m, xs, fp, fp + 3 * m);
+            orc_boris(m, r->c, r->sgn[s], fp, fp + 3 * m, us);
+            orc_move(D, m, r->c, us, xs, dp);
+            orc_zigzag(D, r->n, r->q[s], m, xo, xs, dp, r->J);
+            orc_wrap(D, r->n, m, xs);
+            for (int d = 0; d < D; ++d) memcpy(r->x[s] + d * np + a, xs + d * m, sizeof(double) * (size_t)m);
+            for (int i = 0; i < 3; ++i) memcpy(r->u[s] + i * np + a, us + i * m, sizeof(double) * (size_t)m);
+        }
+        free(xs);
+        free(xo);
+        free(us);
+        free(fp);
+        free(dp);
+        if (!r->ok) break;
+    }
+    return NULL;
+}
+
+struct orc_sum {
+    double *J;
+    double *const *Jt;
+    int64_t a, b;
+    int nthreads;
+};
+
+static void *orc_sum_worker(void *arg)
+{
+    struct orc_sum *r = (struct orc_sum *)arg;
+    for (int64_t k = r->a; k < r->b; ++k) {
+        double acc = 0.0;
+        for (int t = 0; t < r->nthreads; ++t) acc += r->Jt[t][k];
+        r->J[k] = acc;
+    }
+    return NULL;
+}
+
+/* orc_step on nthreads host threads (Table-1 order as orc_step).  Returns
+ * 0, or -1 if memory or threads could not be obtained. */
+int orc_step_threads(int D, const int n[3], double c, int nspecies, const int64_t *n_per,
+                     double **x, double **u, const double *q, const double *sgn,
+                     double *E, double *B, double *J, int nthreads)
+{
+    if (nthreads < 1) nthreads = 1;
+    int64_t N = ncells(n);
+    double **Jt = calloc((size_t)nthreads, sizeof(double *));
+    struct orc_range *rg = calloc((size_t)nthreads, sizeof(struct orc_range));
+    struct orc_sum *sm = calloc((size_t)nthreads, sizeof(struct orc_sum));
+    pthread_t *th = calloc((size_t)nthreads, sizeof(pthread_t));
+    int ok = Jt && rg && sm && th;
+    for (int t = 0; ok && t < nthreads; ++t) {
+        Jt[t] = calloc((size_t)(3 * N), sizeof(double));
+        ok = Jt[t] != NULL;
+    }
+    if (ok) {
+        orc_advance_b(D, n, 0.5 * c, E, B);                       /* push_half_b1 */
+        for (int t = 0; t < nthreads; ++t) {                       /* interp_em, push, comp_curr */
+            struct orc_range r = {D, nspecies, n, c, n_per, x, u, q, sgn, E, B, Jt[t], t, nthreads, 0};
+            rg[t] = r;
+        }
+        int started = 0;
+        for (int t = 0; t < nthreads; ++t) {
+            if (pthread_create(&th[t], NULL, orc_range_worker, &rg[t]) != 0) break;
+            ++started;
+        }
+        for (int t = 0; t < started; ++t) pthread_join(th[t], NULL);
+        ok = started == nthreads;
+        for (int t = 0; ok && t < nthreads; ++t) ok = rg[t].ok;
+    }
+    if (ok) {
+        orc_advance_b(D, n, 0.5 * c, E, B);                       /* push_half_b2 */
+        orc_advance_e(D, n, c, B, E);                             /* push_e */
+        int started = 0;                                           /* J in thread order */
+        for (int t = 0; t < nthreads; ++t) {
+            sm[t].J = J;
+            sm[t].Jt = Jt;
+            part_range(3 * N, t, nthreads, &sm[t].a, &sm[t].b);
+            sm[t].nthreads = nthreads;
+            if (pthread_create(&th[t], NULL, orc_sum_worker, &sm[t]) != 0) break;
+            ++started;
+        }
+        for (int t = 0; t < started; ++t) pthread_join(th[t], NULL);
+        ok = started == nthreads;
+        if (ok) orc_add_current(n, J, E);                         /* add_cur */
+    }
+    for (int t = 0; Jt && t < nthreads; ++t) free(Jt[t]);
+    free(Jt);
+    free(rg);
+    free(sm);
+    free(th);
+    return ok ? 0 : -1;
+}

@@ -22,8 +22,14 @@ permutations, migration counts) can be checked bit-exactly:
   code: sum_d (delta_d + 1) 3^d.
 * cell key: sum_d (floor(x_loc_d) + T_d/2) * prod_{d'<d} T_d' (x fastest);
   the cell sort is a stable sort by this key inside each tile.
-* near-face flag: the local coordinate lies within one unit in the last
-  place (of the storage precision) of an integer.
+* near-face flag: some local coordinate lies within 2 units in the last
+  place of the storage precision at the tile half-width, 2 ulp_p(T_d/2), of
+  an integer (a cell face).  Every coordinate of the tile is at most T_d/2 in
+  size, so this holds every particle within 1 ulp of its own value of a
+  face.
+* migration counts: for every tile and direction code, the particles that
+  were in the tile before the step and are in the neighbour at that offset
+  after it (the centre code: those that stayed).
 """
 from __future__ import annotations
 
@@ -81,13 +87,19 @@ def cell_key(xl, T, D):
     return key
 
 
-def near_face(xl, D):
-    """True where a local coordinate is within 1 ulp of an integer."""
+def near_face_band(T, D, dtype):
+    """Per dimension: 2 ulps of the storage precision at T_d / 2."""
+    return [2.0 * float(np.spacing(dtype(T[d] // 2))) for d in range(D)]
+
+
+def near_face(xl, D, T):
+    """True where some local coordinate lies within the near-face band of an
+    integer (distances computed exactly in FP64)."""
+    band = near_face_band(T, D, xl.dtype.type)
     flag = np.zeros(xl.shape[1], dtype=bool)
     for d in range(D):
-        v = xl[d]
-        dist = np.abs(v.astype(np.float64) - np.round(v.astype(np.float64)))
-        flag |= dist <= np.spacing(np.abs(v)).astype(np.float64)
+        v = xl[d].astype(np.float64)
+        flag |= np.abs(v - np.round(v)) <= band[d]
     return flag
 
 
@@ -128,6 +140,31 @@ def migrate(tile_of, xl, T, D, n):
         new_xl[d] = (xl[d].astype(np.float64) - delta[d] * T[d]).astype(xl.dtype)
     counts = np.bincount(dest, minlength=ntiles)
     return perm, dest[perm], new_xl[:, perm], counts
+
+
+def migration_counts(tile_before, tile_after, n, T, D, ntiles):
+    """Per (tile before, direction code): how many particles moved from the
+    tile to the neighbour at that offset (periodic tile grid), by direct
+    counting over matched particles.  tile_before, tile_after: (np,) tile ids
+    of the same particles before and after the step.  Needs at least 3 tiles
+    along every grid dimension (with 2 the offsets -1 and +1 name the same
+    tile)."""
+    nt = tile_grid(n, T, D)
+    assert all(nt[d] >= 3 for d in range(D)), "direction codes need >= 3 tiles per dimension"
+    a = np.asarray(tile_before, dtype=np.int64)
+    b = np.asarray(tile_after, dtype=np.int64)
+    ca = [a % nt[0], (a // nt[0]) % nt[1], a // (nt[0] * nt[1])]
+    cb = [b % nt[0], (b // nt[0]) % nt[1], b // (nt[0] * nt[1])]
+    code = np.zeros(a.size, dtype=np.int64)
+    for d in range(D):
+        delta = (cb[d] - ca[d]) % nt[d]
+        delta = np.where(delta == nt[d] - 1, -1, delta)   # one step at most
+        if nt[d] == 1:
+            delta = np.zeros_like(delta)
+        code += (delta + 1) * 3 ** d
+    out = np.zeros((ntiles, 3 ** D), dtype=np.int64)
+    np.add.at(out, (a, code), 1)
+    return out
 
 
 def cell_sort(tile_of, xl, T, D):

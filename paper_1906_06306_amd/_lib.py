@@ -28,6 +28,7 @@ PIC_FUSED = 1
 PIC_SORT_CELLS = 2
 PIC_PUSH_HALF_B = 4
 PIC_DEPOSIT_CURL_E = 8
+PIC_ALL_SPECIES = 0xFFFFFFFF
 PIC_OPT_ACC_WORKING = 1
 PIC_OPT_PERSISTENT = 2
 PIC_OPT_TRACK = 4
@@ -100,9 +101,9 @@ def lib():
             "pic_query": [P, P, P],
             "pic_init_tiles": [P, P, P, U64, P, P, P],
             "pic_fdtd_step": [P, I32],
-            "pic_push_interp": [P, U32],
-            "pic_deposit_current": [P, U32],
-            "pic_sort_migrate": [P, U32],
+            "pic_push_interp": [P, U32, U32],
+            "pic_deposit_current": [P, U32, U32],
+            "pic_sort_migrate": [P, U32, P, P, I64],
             "pic_step": [P, U32],
             "pic_filter_current": [P, I32],
             "pic_inject": [P, I32, I32, I64, P, P],

@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -67,6 +68,7 @@ struct Layout {
     uint64_t off_tiles, off_charge, off_qm, off_mass, off_order, off_queue;
     uint64_t off_key, off_xl, off_hist;
     uint64_t off_ob_ids, off_adj_lj, off_adj_eblk, off_adj_bblk, off_ob_boff, off_ob_idx, off_jtmp, off_rho_prev;
+    uint64_t off_nf_pre;
     int64_t fblk_cells, n_input;
     int64_t jblk_cells, rblk_cells, max_count, max_ntb, nchunks_max, ob_dir_stride;
     int32_t order_shift;   // segment counts are bucketed by count >> order_shift for the dispatch order
@@ -231,7 +233,7 @@ pic_status make_layout(const pic_config *c, const int64_t *counts, Layout &L)
     P.off_seg_capacity = take(tiles * ns * 4);
     P.off_seg_count = take(tiles * ns * 4);
     P.off_error = take(4);
-    P.off_flags = take(8);
+    P.off_flags = take(tiles * ns * 4);
     P.off_ids = take(track ? cap_total * 4 : 0);
     L.off_tmp = take((D + 3) * cap_total * w);
     L.off_jblk = take(tiles * ns * 3 * cb * w);
@@ -247,6 +249,7 @@ pic_status make_layout(const pic_config *c, const int64_t *counts, Layout &L)
     L.off_ob_idx = take(tiles * ns * obcap * 4);
     L.off_jtmp = take(3 * cells * w);
     L.off_rho_prev = take(cells * 8);
+    L.off_nf_pre = take(tiles * ns * 8);
     L.off_tiles = take(tiles * sizeof(TileDesc));
     L.off_charge = take(nb * ns * w);
     L.off_qm = take(nb * ns * w);
@@ -294,6 +297,9 @@ struct pic_ctx {
     uint8_t *ws;
     std::vector<double> mass;
     int state;          // 0 ready, 1 unfused push done, 2 fused push done, 3 unfused deposit done
+    uint32_t all_species;   // mask of every species
+    uint32_t pushed;        // species pushed in the current step
+    uint32_t launch_mask;   // species of the next launch (Params::species_mask)
 };
 
 namespace {
@@ -334,7 +340,16 @@ Params<R> params(pic_ctx *x)
     p.ob_dir_stride = L.ob_dir_stride;
     p.tmp = reinterpret_cast<R *>(ws + L.off_tmp);
     p.err = reinterpret_cast<int32_t *>(ws + L.pub.off_error);
-    p.nearface = reinterpret_cast<unsigned long long *>(ws + L.pub.off_flags);
+    p.nf_seg = reinterpret_cast<int32_t *>(ws + L.pub.off_flags);
+    for (int d = 0; d < 3; ++d) {
+        // 2 ulps of R at the tile half-width: every particle within 1 ulp of a
+        // face, and every one that an FP32 step can move across a face
+        // relative to the FP64 step from the same input
+        const R h = (R)(x->T[d] / 2 > 0 ? x->T[d] / 2 : 1);
+        p.nf_band[d] = R(2) * (std::nextafter(h, std::numeric_limits<R>::infinity()) - h);
+    }
+    p.species_mask = x->launch_mask;
+    p.mig_counts = nullptr;
     p.queue = reinterpret_cast<int32_t *>(ws + L.off_queue);
     p.order = reinterpret_cast<int32_t *>(ws + L.off_order);
     if (x->track) {
@@ -374,7 +389,7 @@ struct Impl {
             cbn *= x->T[d] + 3;
         }
         return (3 * cbn + 3 * fbn) * sizeof(R) + (fused ? 3 * cbn * acc_bytes : 0) +
-               2 * PUSH_UNROLL * pic::MAX_WAVES * sizeof(int);
+               (2 * PUSH_UNROLL * pic::MAX_WAVES + 4) * sizeof(int);
     }
 
     template <int ORDER>
@@ -505,9 +520,12 @@ struct Impl {
         return PIC_OK;
     }
 
-    static pic_status migrate(pic_ctx *x, bool need_out, bool need_in, bool sort)
+    static pic_status migrate(pic_ctx *x, bool need_out, bool need_in, bool sort, int32_t *mig_counts,
+                              int64_t *flagged, int64_t flagged_cap)
     {
         Params<R> p = params<R>(x);
+        p.mig_counts = mig_counts;
+        if (need_in) p.species_mask = x->pushed;   // only these species have leavers
         dim3 g((unsigned)x->L.pub.tiles_total);
         if (need_out) {
             hipLaunchKernelGGL((pic::k_migrate_out<R, D>), g, dim3(x->block), 0, x->stream, p);
@@ -526,11 +544,31 @@ struct Impl {
             size_t lds = (size_t)(4 + 1) * ncell * sizeof(int);
             pic_status st = set_lds(pic::k_cell_sort<R, D>, lds);
             if (st) return st;
-            st = fill<unsigned long long>(x, p.nearface, 1, 0ull);
-            if (st) return st;
             hipLaunchKernelGGL((pic::k_cell_sort<R, D>), g, dim3(256), lds, x->stream, p);
             HIP_OK(hipGetLastError());
         }
+        if (flagged) {
+            // per-segment counts of the stored positions, their prefix in
+            // slot order (and the total into flagged[0]), then the slots
+            const int64_t nseg = x->L.pub.tiles_total * x->ns;
+            int64_t *pre = reinterpret_cast<int64_t *>(x->ws + x->L.off_nf_pre);
+            hipLaunchKernelGGL((pic::k_count_near_face<R, D>), dim3((unsigned)nseg), dim3(256), 0, x->stream, p);
+            hipLaunchKernelGGL(pic::k_flag_scan, dim3(1), dim3(1024), 0, x->stream, p.nf_seg, (int32_t)nseg, pre,
+                               flagged);
+            hipLaunchKernelGGL((pic::k_flag_list<R, D>), dim3((unsigned)nseg), dim3(256), 0, x->stream, p, pre,
+                               flagged, flagged_cap);
+            HIP_OK(hipGetLastError());
+        }
+        return PIC_OK;
+    }
+
+    // near-face count of every segment from the stored positions
+    static pic_status count_near_face(pic_ctx *x)
+    {
+        Params<R> p = params<R>(x);
+        hipLaunchKernelGGL((pic::k_count_near_face<R, D>), dim3((unsigned)(x->L.pub.tiles_total * x->ns)), dim3(256),
+                           0, x->stream, p);
+        HIP_OK(hipGetLastError());
         return PIC_OK;
     }
 
@@ -560,8 +598,7 @@ struct Impl {
         g.id_base = id_base;
         g.walls = L.tiles[L.box_tile0[b]].walls != 0 || L.tiles[L.box_tile0[b] + t0.nt[0] - 1].walls != 0;
         int kgrid = (int)std::min<int64_t>((count + 255) / 256, 16384);
-        hipLaunchKernelGGL((pic::k_bin_keys<R, D>), dim3(kgrid), dim3(256), 0, x->stream, g, pos, key, xl, p.err,
-                           p.nearface);
+        hipLaunchKernelGGL((pic::k_bin_keys<R, D>), dim3(kgrid), dim3(256), 0, x->stream, g, pos, key, xl, p.err);
         // per-chunk tile histograms in LDS up to 32,768 tiles per box, else
         // in global memory (zeroed here)
         g.hist_lds = g.ntb <= 32768;
@@ -583,7 +620,8 @@ struct Impl {
 
     static pic_status inject(pic_ctx *x, int b, int s, int64_t count, const double *pos, const double *u)
     {
-        return bin_species(x, b, s, count, pos, u, -1);
+        pic_status st = bin_species(x, b, s, count, pos, u, -1);
+        return st ? st : count_near_face(x);
     }
 
     static pic_status init(pic_ctx *x, const int64_t *counts, const pic_init_data *in)
@@ -623,7 +661,7 @@ struct Impl {
             hipLaunchKernelGGL((pic::k_hold_walls<R, D>), dim3((unsigned)L.pub.tiles_total), dim3(256), 0, x->stream, p);
             HIP_OK(hipGetLastError());
         }
-        return PIC_OK;
+        return count_near_face(x);
     }
 
     // Reverse of one fused step from the current state (Table 1 rows in
@@ -717,8 +755,6 @@ struct Impl {
         HIP_OK(hipGetLastError());
         std::vector<double> h(L.pub.tiles_total * pic::NPART);
         HIP_OK(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, x->stream));
-        unsigned long long nf = 0;
-        HIP_OK(hipMemcpyAsync(&nf, p.nearface, sizeof nf, hipMemcpyDeviceToHost, x->stream));
         HIP_OK(hipStreamSynchronize(x->stream));
         const int nout = per_box ? x->nb : 1;
         memset(out, 0, nout * sizeof *out);
@@ -731,11 +767,9 @@ struct Impl {
             d->particles += (int64_t)o[3];
             d->gauss_max = std::max(d->gauss_max, o[4]);
             d->charge_total += o[5];
+            d->near_face += (int64_t)o[7];
         }
-        for (int k = 0; k < nout; ++k) {
-            out[k].near_face = (int64_t)nf;
-            out[k].continuity_max = cont_valid ? 0.0 : -1.0;
-        }
+        for (int k = 0; k < nout; ++k) out[k].continuity_max = cont_valid ? 0.0 : -1.0;
         if (cont_valid)
             for (int64_t t = 0; t < L.pub.tiles_total; ++t) {
                 pic_diag *d = per_box ? out + L.tiles[t].box : out;
@@ -767,7 +801,10 @@ pic_status do_init(pic_ctx *x, const int64_t *counts, const pic_init_data *in) {
 pic_status do_fdtd(pic_ctx *x, int phase) { PIC_DISPATCH(x, fdtd(x, phase)); }
 pic_status do_push(pic_ctx *x, bool fused, bool halfb) { PIC_DISPATCH(x, push(x, fused, halfb)); }
 pic_status do_deposit(pic_ctx *x, bool unfused, bool curl_e) { PIC_DISPATCH(x, deposit(x, unfused, curl_e)); }
-pic_status do_migrate(pic_ctx *x, bool out, bool in, bool sort) { PIC_DISPATCH(x, migrate(x, out, in, sort)); }
+pic_status do_migrate(pic_ctx *x, bool out, bool in, bool sort, int32_t *mc, int64_t *fl, int64_t fcap)
+{
+    PIC_DISPATCH(x, migrate(x, out, in, sort, mc, fl, fcap));
+}
 pic_status do_diag(pic_ctx *x, pic_diag *o, bool per_box) { PIC_DISPATCH(x, diag(x, o, per_box)); }
 pic_status do_adjoint(pic_ctx *x, void *a, void *b, void *c, void *d) { PIC_DISPATCH(x, adjoint(x, a, b, c, d)); }
 pic_status do_filter(pic_ctx *x, int passes) { PIC_DISPATCH(x, filter(x, passes)); }
@@ -885,6 +922,9 @@ pic_status pic_init_tiles(const pic_config *cfg, const int64_t *counts, void *wo
     x->stream = reinterpret_cast<hipStream_t>(hip_stream);
     x->ws = reinterpret_cast<uint8_t *>(workspace);
     x->state = 0;
+    x->all_species = (1u << x->ns) - 1u;
+    x->pushed = 0;
+    x->launch_mask = x->all_species;
     const Layout &L = x->L;
     auto cleanup = [&](pic_status s) {
         delete x;
@@ -904,8 +944,6 @@ pic_status pic_init_tiles(const pic_config *cfg, const int64_t *counts, void *wo
     st = x->prec == PIC_FP32 ? upload_tables<float>(x, cfg) : upload_tables<double>(x, cfg);
     if (st) return cleanup(st);
     if ((st = fill<int32_t>(x, reinterpret_cast<int32_t *>(x->ws + L.pub.off_error), 1, 0))) return cleanup(st);
-    if ((st = fill<unsigned long long>(x, reinterpret_cast<unsigned long long *>(x->ws + L.pub.off_flags), 1, 0ull)))
-        return cleanup(st);
     if ((st = do_init(x, counts, init))) return cleanup(st);
     int32_t bits = 0;
     if ((st = read_error(x, &bits))) return cleanup(st);
@@ -921,49 +959,78 @@ pic_status pic_fdtd_step(pic_ctx *x, int32_t phase)
     return do_fdtd(x, phase);
 }
 
-pic_status pic_push_interp(pic_ctx *x, uint32_t flags)
+// species mask of a push or deposit call: PIC_ALL_SPECIES or a nonempty
+// subset of the context's species
+static pic_status species_of(pic_ctx *x, uint32_t mask, uint32_t *out)
+{
+    if (mask == PIC_ALL_SPECIES) mask = x->all_species;
+    if (!mask || (mask & ~x->all_species))
+        return fail(PIC_E_ARG, "species mask 0x%x: empty or beyond the %d species", mask, x->ns);
+    if (x->track && mask != x->all_species)
+        return fail(PIC_E_ARG, "origin tracking (PIC_OPT_TRACK) needs every species in one call");
+    *out = mask;
+    return PIC_OK;
+}
+
+pic_status pic_push_interp(pic_ctx *x, uint32_t species_mask, uint32_t flags)
 {
     if (!x) return fail(PIC_E_ARG, "null context");
-    if (x->state != 0) return fail(PIC_E_STATE, "push called before the previous push was deposited and migrated");
+    uint32_t mask = 0;
+    pic_status st = species_of(x, species_mask, &mask);
+    if (st) return st;
     const bool fused = flags & PIC_FUSED;
+    if (x->state >= 3) return fail(PIC_E_STATE, "push called after this step's deposit");
+    if (x->state != 0 && (x->state == 2) != fused)
+        return fail(PIC_E_STATE, "every push of a step must use the same PIC_FUSED setting");
+    if (x->pushed & mask) return fail(PIC_E_STATE, "species 0x%x already pushed in this step", x->pushed & mask);
     if (x->order == 4 && (flags & PIC_PUSH_HALF_B))
         return fail(PIC_E_ARG, "PIC_PUSH_HALF_B applies the second-order half update; use pic_fdtd_step with FDTD4");
     if (x->track && !fused) return fail(PIC_E_ARG, "origin tracking records origins in the fused push only");
     if (x->walls && !fused) return fail(PIC_E_ARG, "boxes with walls need the fused push (PIC_FUSED)");
-    pic_status st = do_push(x, fused, (flags & PIC_PUSH_HALF_B) != 0);
+    x->launch_mask = mask;
+    st = do_push(x, fused, (flags & PIC_PUSH_HALF_B) != 0);
+    x->launch_mask = x->all_species;
     if (st) return st;
+    x->pushed |= mask;
     x->state = fused ? 2 : 1;
     return PIC_OK;
 }
 
-pic_status pic_deposit_current(pic_ctx *x, uint32_t flags)
+pic_status pic_deposit_current(pic_ctx *x, uint32_t species_mask, uint32_t flags)
 {
     if (!x) return fail(PIC_E_ARG, "null context");
+    uint32_t mask = 0;
+    pic_status st = species_of(x, species_mask, &mask);
+    if (st) return st;
     const bool curl_e = flags & PIC_DEPOSIT_CURL_E;
     if (curl_e && x->order != 2) return fail(PIC_E_ARG, "PIC_DEPOSIT_CURL_E applies the second-order E update; use pic_fdtd_step with FDTD4");
-    if (x->state == 1) {
-        pic_status st = do_deposit(x, true, curl_e);
-        if (st) return st;
-        x->state = 3;
-        return PIC_OK;
-    }
-    if (x->state == 2) return do_deposit(x, false, curl_e);
-    return fail(PIC_E_STATE, "deposit needs a preceding push");
+    if (x->state != 1 && x->state != 2) return fail(PIC_E_STATE, "deposit needs a preceding push (once per step)");
+    if (mask & ~x->pushed) return fail(PIC_E_STATE, "species 0x%x not pushed in this step", mask & ~x->pushed);
+    x->launch_mask = mask;
+    st = do_deposit(x, x->state == 1, curl_e);
+    x->launch_mask = x->all_species;
+    if (st) return st;
+    x->state = 3 + (x->state == 2 ? 1 : 0);   // 3: unfused deposited, 4: fused deposited
+    return PIC_OK;
 }
 
-pic_status pic_sort_migrate(pic_ctx *x, uint32_t flags)
+pic_status pic_sort_migrate(pic_ctx *x, uint32_t flags, int32_t *migration_counts, int64_t *flagged,
+                            int64_t flagged_capacity)
 {
     if (!x) return fail(PIC_E_ARG, "null context");
     if (x->state == 1) return fail(PIC_E_STATE, "deposit the current of an unfused push before migrating");
+    if (flagged_capacity < 0) return fail(PIC_E_ARG, "flagged_capacity must be >= 0");
     const bool sort = flags & PIC_SORT_CELLS;
     if (x->track && sort) return fail(PIC_E_ARG, "the cell sort does not record origins (PIC_OPT_TRACK)");
+    const bool stepped = x->state != 0;
+    if (migration_counts && !stepped) return fail(PIC_E_STATE, "migration counts need a preceding push");
     pic_status st;
-    const bool stepped = x->state == 2 || x->state == 3;
-    if (x->state == 3) st = do_migrate(x, true, true, sort);        // unfused push: out + in
-    else if (x->state == 2) st = do_migrate(x, false, true, sort);  // fused push packed already
-    else st = sort ? do_migrate(x, false, false, true) : PIC_OK;    // nothing moved: sort only
+    if (x->state == 3) st = do_migrate(x, true, true, sort, migration_counts, flagged, flagged_capacity);
+    else if (stepped) st = do_migrate(x, false, true, sort, migration_counts, flagged, flagged_capacity);
+    else st = do_migrate(x, false, false, sort, nullptr, flagged, flagged_capacity);   // nothing moved
     if (st) return st;
     x->state = 0;
+    x->pushed = 0;
     if (stepped) ++x->steps;
     return PIC_OK;
 }
@@ -973,8 +1040,8 @@ pic_status pic_sort_migrate(pic_ctx *x, uint32_t flags)
 static pic_status current_and_e(pic_ctx *x, uint32_t flags)
 {
     pic_status st;
-    if (!x->filter_passes && x->order == 2) return pic_deposit_current(x, flags | PIC_DEPOSIT_CURL_E);
-    if ((st = pic_deposit_current(x, flags))) return st;
+    if (!x->filter_passes && x->order == 2) return pic_deposit_current(x, PIC_ALL_SPECIES, flags | PIC_DEPOSIT_CURL_E);
+    if ((st = pic_deposit_current(x, PIC_ALL_SPECIES, flags))) return st;
     if (x->filter_passes && (st = pic_filter_current(x, x->filter_passes))) return st;
     return pic_fdtd_step(x, PIC_CURL_E_ADD_J);
 }
@@ -988,16 +1055,16 @@ pic_status pic_step(pic_ctx *x, uint32_t flags)
     if (flags & PIC_PUSH_HALF_B) {
         // push_half_b1 happens inside the push on its LDS copy of B; both
         // half updates are then applied to the stored B in one pass
-        if ((st = pic_push_interp(x, flags))) return st;
+        if ((st = pic_push_interp(x, PIC_ALL_SPECIES, flags))) return st;
         if ((st = pic_fdtd_step(x, PIC_TWO_HALF_B))) return st;
         if ((st = current_and_e(x, flags))) return st;
-        return pic_sort_migrate(x, flags);
+        return pic_sort_migrate(x, flags, nullptr, nullptr, 0);
     }
     if ((st = pic_fdtd_step(x, PIC_HALF_B))) return st;
-    if ((st = pic_push_interp(x, flags))) return st;
+    if ((st = pic_push_interp(x, PIC_ALL_SPECIES, flags))) return st;
     if ((st = pic_fdtd_step(x, PIC_HALF_B))) return st;
     if ((st = current_and_e(x, flags))) return st;
-    return pic_sort_migrate(x, flags);
+    return pic_sort_migrate(x, flags, nullptr, nullptr, 0);
 }
 
 pic_status pic_inject(pic_ctx *x, int32_t box, int32_t species, int64_t count, const double *pos, const double *u)

@@ -93,24 +93,14 @@ struct BinGeom {
     int32_t hist_lds;     // per-chunk tile histograms fit in LDS (else they stay in global memory)
 };
 
-template <typename R>
-__device__ __forceinline__ bool near_face_value(R v)
-{
-    R av = fabs(v);
-    R ulp = nextafter(av, R(INFINITY)) - av;
-    return fabs(v - rint(v)) <= ulp;
-}
-
 // Tile key and tile-centre-relative position of every particle.
 template <typename R, int D>
-__global__ void k_bin_keys(BinGeom g, const double *pos, int32_t *key, R *xl, int32_t *err,
-                           unsigned long long *nearface)
+__global__ void k_bin_keys(BinGeom g, const double *pos, int32_t *key, R *xl, int32_t *err)
 {
-    unsigned long long nf = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < g.count;
          i += (int64_t)gridDim.x * blockDim.x) {
         int tc[3] = {0, 0, 0};
-        bool ok = true, flag = false;
+        bool ok = true;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             double x = pos[d * g.count + i];
@@ -130,7 +120,6 @@ __global__ void k_bin_keys(BinGeom g, const double *pos, int32_t *key, R *xl, in
             }
             tc[d] = t;
             xl[d * g.count + i] = loc;
-            flag = flag || near_face_value<R>(loc);
         }
         if (!ok) {
             latch(err, ERR_OUT_OF_TILE);
@@ -138,9 +127,7 @@ __global__ void k_bin_keys(BinGeom g, const double *pos, int32_t *key, R *xl, in
         } else {
             key[i] = tc[0] + g.nt[0] * (tc[1] + g.nt[1] * tc[2]);
         }
-        nf += flag;
     }
-    if (nf) atomicAdd(nearface, nf);
 }
 
 // Zero the wall planes (Ey, Ez, Bx at x = 0) of the tiles on a low-x wall.
@@ -289,8 +276,9 @@ __device__ __forceinline__ double wg_max(double v, double *sh)
 
 constexpr int NPART = 8;   // partial values per tile
 
-// Per tile: field energy, max |div+ B|, kinetic energy, particle count, and
-// the cloud-in-cell charge block (nodes 0..T per dimension, FP64).
+// Per tile: field energy, max |div+ B|, kinetic energy, particle count, the
+// near-face count, and the cloud-in-cell charge block (nodes 0..T per
+// dimension, FP64).
 template <typename R, int D>
 __global__ void __launch_bounds__(256) k_diag_tile(Params<R> p, const double *mass, double *part, double *rblk)
 {
@@ -376,6 +364,9 @@ __global__ void __launch_bounds__(256) k_diag_tile(Params<R> p, const double *ma
         o[1] = m_db;
         o[2] = c2 * s_ek;
         o[3] = s_np;
+        double nf = 0;
+        for (int s = 0; s < p.nspecies; ++s) nf += p.nf_seg[t * p.nspecies + s];
+        o[7] = nf;
     }
     __syncthreads();
     double *blk = rblk + (int64_t)t * nr;

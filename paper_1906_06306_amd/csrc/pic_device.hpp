@@ -55,7 +55,10 @@ struct Params {
     int64_t ob_dir_stride;    // slots per outbox direction list (ob_cap)
     R *tmp;                   // sort staging [(D+3)][cap_total]
     int32_t *err;             // latched error bits
-    unsigned long long *nearface;
+    int32_t *nf_seg;          // [tile*species] particles flagged near a cell face
+    R nf_band[3];             // near-face band per dimension: 2 ulp(T_d/2) in R
+    uint32_t species_mask;    // species the launch works on (bit s = species s)
+    int32_t *mig_counts;      // [tile*species][ncodes] migration counts, or null
     int32_t *queue;           // work counter of the persistent walker
     int32_t *order;           // (tile, species) segments in visiting order
     int32_t *ids;             // [cap_total] origin of each particle, or null
@@ -116,6 +119,18 @@ __device__ __forceinline__ int ext(const int32_t T[3], int d, int halo)
 __device__ __forceinline__ int lanes_below(unsigned long long mask)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Near-face flag of a stored tile-local position: some grid coordinate lies
+// within band_d of an integer (a cell face).  x - rint(x) is exact in R, so
+// the test is the same in any precision that holds x exactly.
+template <typename R, int D>
+__device__ __forceinline__ bool near_face(const R x[3], const R band[3])
+{
+    bool f = false;
+#pragma unroll
+    for (int d = 0; d < D; ++d) f = f || fabs(x[d] - rint(x[d])) <= band[d];
+    return f;
 }
 
 __device__ __forceinline__ void latch(int32_t *err, int32_t bits)

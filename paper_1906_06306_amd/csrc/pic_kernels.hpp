@@ -171,6 +171,7 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int w, unsig
 {
     // work item w = one (tile, species) segment
     const int t = w / p.nspecies, s = w - t * p.nspecies;
+    if (!((p.species_mask >> s) & 1u)) return;   // species not pushed by this call
     const TileDesc td = p.tiles[t];
     // tile edge: a compile-time constant when TC > 0 (strides, LDS offsets
     // and the halves T/2 then fold into the instructions), else the runtime one
@@ -190,6 +191,8 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int w, unsig
     R *sE = reinterpret_cast<R *>(sJ + (FUSED ? 3 * cb.n : 0));
     R *sB = sE + 3 * cb.n;
     int *sTot = reinterpret_cast<int *>(sB + 3 * fb.n);
+    int *sNF = sTot + 2 * U * MAX_WAVES;   // particles left near a cell face
+    if (threadIdx.x == 0) *sNF = 0;
     stage_block<R, D>(p.E, p.cells_total, td, T, sE, cb);
     stage_block<R, D>(p.B, p.cells_total, td, T, sB, fb);
     if constexpr (FUSED) {
@@ -211,6 +214,7 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int w, unsig
     const int G = U * blockDim.x;
     int parity = 0;
     int32_t errs = 0;
+    int nfl = 0;         // this thread's particles left near a cell face
     int fx = 0;          // fixed-point exponent of the current block
     R qd;
     {
@@ -327,6 +331,9 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int w, unsig
 #pragma unroll
                     for (int d = 0; d < D; ++d) x2[j][d] = x[j][d];
                 }
+                // rebasing by -delta T (an even integer) is exact and keeps
+                // the distance to the nearest face
+                nfl += near_face<R, D>(x2[j], p.nf_band);
             }
             if constexpr (FUSED) {
                 // stable compaction: stayers in place (every destination is at
@@ -393,8 +400,15 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int w, unsig
         }
     }
     latch_wave(p.err, errs);
+    {
+        int v = nfl;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if ((threadIdx.x & 63) == 0 && v) atomicAdd(sNF, v);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) p.nf_seg[w] = *sNF;
     if constexpr (FUSED) {
-        __syncthreads();
         R *blk = p.jblk + (int64_t)w * 3 * cb.n;
         if constexpr (std::is_same<A, long long>::value) {
             const double inv = ldexp(1.0, -fx);
@@ -441,6 +455,7 @@ __global__ void __launch_bounds__(1024) k_deposit(Params<R> p)
     extern __shared__ __align__(16) unsigned char smem[];
     const int w = p.order[blockIdx.x];              // (tile, species) segment
     const int t = w / p.nspecies, s = w - t * p.nspecies;
+    if (!((p.species_mask >> s) & 1u)) return;       // species not deposited by this call
     const TileDesc td = p.tiles[t];
     const CurBox<D> cb(p.T);
     A *sJ = reinterpret_cast<A *>(smem);
@@ -502,7 +517,7 @@ __device__ __forceinline__ void curl_b_update_e(const Params<R> &p, const TileDe
 }
 
 // cur_exchange: J on the lattice = sum of the current blocks (one per
-// species) of the tile and of its neighbours whose halo covers the cell, in
+// species of species_mask) of the tile and of its neighbours whose halo covers the cell, in
 // a fixed order (species, then neighbour offsets ascending, z major).  A
 // block covers local cells -1..T+1, so along each dimension a cell is
 // covered by its own tile and, for l < 2, the tile below or, for l = T-1,
@@ -561,6 +576,7 @@ __global__ void __launch_bounds__(256) k_fold(Params<R> p, R h)
                 base[cmb] = (int64_t)nid * p.nspecies;
             }
             for (int sp = 0; sp < p.nspecies; ++sp) {
+                if (!((p.species_mask >> sp) & 1u)) continue;
                 R v[NCOMB][3];
 #pragma unroll
                 for (int cmb = 0; cmb < NCOMB; ++cmb) {
@@ -575,7 +591,8 @@ __global__ void __launch_bounds__(256) k_fold(Params<R> p, R h)
                 }
             }
         } else {
-            for (int sp = 0; sp < p.nspecies; ++sp)
+            for (int sp = 0; sp < p.nspecies; ++sp) {
+                if (!((p.species_mask >> sp) & 1u)) continue;
                 for (int oz = (D > 2 ? -1 : 0); oz <= (D > 2 ? 1 : 0); ++oz)
                     for (int oy = (D > 1 ? -1 : 0); oy <= (D > 1 ? 1 : 0); ++oy)
                         for (int ox = -1; ox <= 1; ++ox) {
@@ -597,6 +614,7 @@ __global__ void __launch_bounds__(256) k_fold(Params<R> p, R h)
                             acc[1] += blk[cb.n + idx];
                             acc[2] += blk[2 * cb.n + idx];
                         }
+            }
         }
         const int gx = td.tc[0] * T0 + l[0];
         const int gy = D > 1 ? td.tc[1] * T1 + l[1] : 0;
@@ -759,6 +777,7 @@ __global__ void __launch_bounds__(1024) k_migrate_out(Params<R> p)
     const int64_t cap = p.cap_total;
     int parity = 0;
     for (int s = 0; s < p.nspecies; ++s) {
+        if (!((p.species_mask >> s) & 1u)) continue;   // not pushed: every particle stayed
         const int ts = t * p.nspecies + s;
         const int64_t so = p.seg_off[ts];
         const int cnt = p.seg_cnt[ts];
@@ -788,7 +807,8 @@ __global__ void __launch_bounds__(1024) k_migrate_out(Params<R> p)
 // Bucket every tile's outbox by direction code (stable counting sort): for
 // each (tile, species) the bucket starts ob_boff[ncodes + 1] and the outbox
 // slots in bucket order ob_idx[ob_cap], so that each neighbour reads exactly
-// the leavers addressed to it.  The rank of an entry among equal codes of
+// the leavers addressed to it.  With mig_counts, also the segment's
+// migration counts by direction code.  The rank of an entry among equal codes of
 // its wave comes from ballots on the code bits; waves are ordered through
 // per-wave counts in LDS.
 template <typename R, int D>
@@ -801,7 +821,10 @@ __global__ void __launch_bounds__(1024) k_migrate_bucket(Params<R> p)
     const int ts = xcd_tile(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     {
-        const int n = (int)min((int64_t)p.ob_cnt[ts], p.ob_cap);
+        // species_mask: the species pushed in this step; the outboxes of the
+        // others hold nothing of this step
+        const int s = ts % p.nspecies;
+        const int n = ((p.species_mask >> s) & 1u) ? (int)min((int64_t)p.ob_cnt[ts], p.ob_cap) : 0;
         const int32_t *dir = p.ob_dir + (int64_t)ts * p.ob_dir_stride;
         int32_t *boff = p.ob_boff + (int64_t)ts * (NC + 1);
         int32_t *idx = p.ob_idx + (int64_t)ts * p.ob_cap;
@@ -813,6 +836,13 @@ __global__ void __launch_bounds__(1024) k_migrate_bucket(Params<R> p)
         if (threadIdx.x == 0) {
             for (int c = 0; c < NC; ++c) sBase[c + 1] += sBase[c];
             for (int c = 0; c <= NC; ++c) boff[c] = sBase[c];
+            if (p.mig_counts) {
+                // particles of the segment by the tile they went to: the
+                // outbox buckets, and the stayers at the centre code (the
+                // segment count before the arrivals are appended)
+                int32_t *mc = p.mig_counts + (int64_t)ts * NC;
+                for (int c = 0; c < NC; ++c) mc[c] = c == centre_code<D>() ? p.seg_cnt[ts] : sBase[c + 1] - sBase[c];
+            }
         }
         __syncthreads();
         // stable scatter, one work-group-wide chunk at a time
@@ -941,16 +971,16 @@ __global__ void __launch_bounds__(256) k_cell_sort(Params<R> p)
     const int T0 = p.T[0], T1 = D > 1 ? p.T[1] : 1, T2 = D > 2 ? p.T[2] : 1;
     const int ncell = T0 * T1 * T2;
     int *hist = reinterpret_cast<int *>(smem);      // [nw][ncell]
-    __shared__ unsigned long long nf_block;
+    __shared__ int nf_block;
     int nbits = 0;
     while ((1 << nbits) < ncell) ++nbits;
     const int64_t cap = p.cap_total;
-    if (threadIdx.x == 0) nf_block = 0;
     for (int s = 0; s < p.nspecies; ++s) {
         const int ts = t * p.nspecies + s;
         const int64_t so = p.seg_off[ts];
         const int cnt = p.seg_cnt[ts];
         const int per = (cnt + nw - 1) / nw;
+        if (threadIdx.x == 0) nf_block = 0;
         const int lo = min(cnt, wave * per), hi = min(cnt, lo + per);
         for (int k = threadIdx.x; k < nw * ncell; k += blockDim.x) hist[k] = 0;
         __syncthreads();
@@ -1017,25 +1047,108 @@ __global__ void __launch_bounds__(256) k_cell_sort(Params<R> p)
         }
         __threadfence_block();
         __syncthreads();
-        unsigned long long nf = 0;
+        int nf = 0;
         for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-            bool flag = false;
+            R v[3] = {0, 0, 0};
 #pragma unroll
             for (int d = 0; d < D; ++d) {
-                R v = p.tmp[d * cap + so + i];
-                p.pos[d * cap + so + i] = v;
-                R av = fabs(v);
-                R ulp = nextafter(av, R(INFINITY)) - av;
-                flag = flag || fabs(v - rint(v)) <= ulp;
+                v[d] = p.tmp[d * cap + so + i];
+                p.pos[d * cap + so + i] = v[d];
             }
 #pragma unroll
             for (int mm = 0; mm < 3; ++mm) p.u[mm * cap + so + i] = p.tmp[(D + mm) * cap + so + i];
-            nf += flag;
+            nf += near_face<R, D>(v, p.nf_band);
         }
         if (nf) atomicAdd(&nf_block, nf);
         __syncthreads();
+        if (threadIdx.x == 0) p.nf_seg[ts] = nf_block;
     }
-    if (threadIdx.x == 0 && nf_block) atomicAdd(p.nearface, nf_block);
+}
+
+// Near-face count of every segment from its stored positions (after init,
+// an injection, or before listing the flagged particles).
+template <typename R, int D>
+__global__ void __launch_bounds__(256) k_count_near_face(Params<R> p)
+{
+    __shared__ int sN;
+    const int ts = blockIdx.x;
+    const int64_t so = p.seg_off[ts];
+    const int cnt = p.seg_cnt[ts];
+    if (threadIdx.x == 0) sN = 0;
+    __syncthreads();
+    int nf = 0;
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+        R v[3] = {0, 0, 0};
+#pragma unroll
+        for (int d = 0; d < D; ++d) v[d] = p.pos[d * p.cap_total + so + i];
+        nf += near_face<R, D>(v, p.nf_band);
+    }
+    for (int o = 32; o > 0; o >>= 1) nf += __shfl_xor(nf, o);
+    if ((threadIdx.x & 63) == 0 && nf) atomicAdd(&sN, nf);
+    __syncthreads();
+    if (threadIdx.x == 0) p.nf_seg[ts] = sN;
+}
+
+// Exclusive prefix of the per-segment near-face counts (segment order, which
+// is slot order) into pre, and the total into out[0].  One work-group.
+__global__ void __launch_bounds__(1024) k_flag_scan(const int32_t *nf, int32_t n, int64_t *pre, int64_t *out)
+{
+    __shared__ int64_t wsum[16];
+    __shared__ int64_t carry;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < n; base += 1024) {
+        const int64_t v = base + tid < n ? nf[base + tid] : 0;
+        int64_t x = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wv] = x;
+        __syncthreads();
+        int64_t before = carry;
+        for (int w = 0; w < wv; ++w) before += wsum[w];
+        if (base + tid < n) pre[base + tid] = before + x - v;
+        __syncthreads();
+        if (tid == 0) {
+            int64_t tot = 0;
+            for (int w = 0; w < 16; ++w) tot += wsum[w];
+            carry += tot;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) out[0] = carry;
+}
+
+// Slots of the flagged particles, segment by segment in slot order, after
+// k_flag_scan: flagged[1 + k] for k < capacity.  One work-group per segment;
+// the order inside a segment comes from wave ballots and per-wave totals.
+template <typename R, int D>
+__global__ void __launch_bounds__(256) k_flag_list(Params<R> p, const int64_t *pre, int64_t *flagged, int64_t capacity)
+{
+    __shared__ int sTot[2 * MAX_WAVES];
+    const int ts = blockIdx.x;
+    const int64_t so = p.seg_off[ts];
+    const int cnt = p.seg_cnt[ts];
+    int64_t run = pre[ts];
+    int parity = 0;
+    for (int c0 = 0; c0 < cnt; c0 += blockDim.x) {
+        const int i = c0 + threadIdx.x;
+        bool f = false;
+        if (i < cnt) {
+            R v[3] = {0, 0, 0};
+#pragma unroll
+            for (int d = 0; d < D; ++d) v[d] = p.pos[d * p.cap_total + so + i];
+            f = near_face<R, D>(v, p.nf_band);
+        }
+        int tot;
+        const int k = wg_scan_flag(f, sTot, parity, tot);
+        parity ^= 1;
+        if (f && run + k < capacity) flagged[1 + run + k] = so + i;
+        run += tot;
+    }
 }
 
 }  // namespace pic

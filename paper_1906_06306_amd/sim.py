@@ -175,9 +175,20 @@ class PicSim:
     def fdtd(self, phase: int):
         L.check(L.lib().pic_fdtd_step(self.ctx, phase))
 
-    def push(self, fused: bool = True, half_b: bool = False):
+    def push(self, fused: bool = True, half_b: bool = False, species=None):
+        """interp_em + push of the species in `species` (iterable of
+        indices; None: every species)."""
         flags = (L.PIC_FUSED if fused else 0) | (L.PIC_PUSH_HALF_B if half_b else 0)
-        L.check(L.lib().pic_push_interp(self.ctx, flags))
+        L.check(L.lib().pic_push_interp(self.ctx, self._mask(species), flags))
+
+    @staticmethod
+    def _mask(species) -> int:
+        if species is None:
+            return L.PIC_ALL_SPECIES
+        m = 0
+        for s in species:
+            m |= 1 << int(s)
+        return m
 
     def inject(self, box: int, species: int, pos, u):
         """Append particles (FP64 global positions (D, k), four-velocities
@@ -191,11 +202,37 @@ class PicSim:
     def filter_current(self, passes: int):
         L.check(L.lib().pic_filter_current(self.ctx, int(passes)))
 
-    def deposit(self):
-        L.check(L.lib().pic_deposit_current(self.ctx, 0))
+    def deposit(self, species=None, curl_e: bool = False):
+        flags = L.PIC_DEPOSIT_CURL_E if curl_e else 0
+        L.check(L.lib().pic_deposit_current(self.ctx, self._mask(species), flags))
 
-    def sort_migrate(self, sort_cells: bool = False):
-        L.check(L.lib().pic_sort_migrate(self.ctx, L.PIC_SORT_CELLS if sort_cells else 0))
+    def sort_migrate(self, sort_cells: bool = False, counts: bool = False, flagged_capacity: int = -1):
+        """Particle communication (and the cell sort).  counts=True returns
+        the migration counts [tiles][species][3^D] (int32 numpy);
+        flagged_capacity >= 0 also returns (total, slots) of the particles
+        flagged near a cell face afterwards."""
+        mc = fl = None
+        if counts:
+            mc = torch.zeros(int(self.layout.tiles_total) * self.ns * 3 ** self.D, dtype=torch.int32,
+                             device=self.device)
+        if flagged_capacity >= 0:
+            fl = torch.full((flagged_capacity + 1,), -1, dtype=torch.int64, device=self.device)
+        # the outputs are written on the library's stream
+        torch.cuda.current_stream(self.device).synchronize()
+        L.check(L.lib().pic_sort_migrate(self.ctx, L.PIC_SORT_CELLS if sort_cells else 0,
+                                         None if mc is None else mc.data_ptr(),
+                                         None if fl is None else fl.data_ptr(), max(flagged_capacity, 0)))
+        if mc is None and fl is None:
+            return None
+        self.stream.synchronize()
+        out = []
+        if mc is not None:
+            out.append(mc.view(-1, self.ns, 3 ** self.D).cpu().numpy())
+        if fl is not None:
+            h = fl.cpu().numpy()
+            n = int(h[0])
+            out.append((n, h[1:1 + min(n, flagged_capacity)]))
+        return out[0] if len(out) == 1 else tuple(out)
 
     def step(self, n: int = 1, fused: bool = True, sort_cells: bool = False, half_b_in_push: bool = False):
         flags = ((L.PIC_FUSED if fused else 0) | (L.PIC_SORT_CELLS if sort_cells else 0)

@@ -137,8 +137,9 @@ def test_adjoint_requires_tracking():
         == L.PIC_E_STATE
     sim.close()
     sim = make_sim(plasma, (8, 8), "fp64")
-    assert L.lib().pic_sort_migrate(sim.ctx, L.PIC_SORT_CELLS) == L.PIC_E_ARG
-    assert L.lib().pic_push_interp(sim.ctx, 0) == L.PIC_E_ARG
+    assert L.lib().pic_sort_migrate(sim.ctx, L.PIC_SORT_CELLS, None, None, 0) == L.PIC_E_ARG
+    assert L.lib().pic_push_interp(sim.ctx, L.PIC_ALL_SPECIES, 0) == L.PIC_E_ARG
+    assert L.lib().pic_push_interp(sim.ctx, 1, L.PIC_FUSED) == L.PIC_E_ARG   # every species with tracking
     sim.close()
 
 

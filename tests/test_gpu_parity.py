@@ -71,7 +71,7 @@ def test_init_binning_bit_exact(D, n, T, ppc, prec):
     assert np.array_equal(E, plasma.E.astype(dt).astype(np.float64))
     assert not J.any()
     d = sim.diagnostics()
-    flags = sum(int(tiles.near_face(sim.particles_host(0, s)[1], D).sum()) for s in range(2))
+    flags = sum(int(tiles.near_face(sim.particles_host(0, s)[1], D, T).sum()) for s in range(2))
     assert d["near_face"] == flags
     sim.close()
 
@@ -123,9 +123,11 @@ def test_unfused_step_stage_by_stage(D, n, T, ppc, prec):
     E, _, _ = sim.fields_host(0)
     assert rel(E, st.E) < tol
     # particle communication: bit-exact against the rule applied to the
-    # GPU's own pushed positions
+    # GPU's own pushed positions; migration counts by direct counting over
+    # the particles matched through the rule's permutation
     before = [sim.particles_host(0, s) for s in range(2)]
-    sim.sort_migrate()
+    mc = sim.sort_migrate(counts=True)
+    nt = tiles.tile_grid(n, T, D)
     for s in range(2):
         tid, xl, u = before[s]
         perm, ntid, nxl, counts = tiles.migrate(tid, xl, T, D, n)
@@ -134,6 +136,10 @@ def test_unfused_step_stage_by_stage(D, n, T, ppc, prec):
         assert np.array_equal(g_xl, nxl)
         assert np.array_equal(g_u, u[:, perm])
         assert np.array_equal(np.bincount(g_tid, minlength=counts.size), counts)
+        if min(nt[:D]) >= 3:
+            want = tiles.migration_counts(tid[perm], ntid, n, T, D, counts.size)
+            assert np.array_equal(mc[:, s, :], want)
+        assert mc[:, s, :].sum() == tid.size
     assert sim.error() == 0
     sim.close()
 
@@ -217,7 +223,7 @@ def test_fold_with_e_update_is_refused_under_fdtd4():
     sim.push(fused=True)
     sim.fdtd(L.PIC_HALF_B)
     with pytest.raises(L.PicError) as e:
-        L.check(L.lib().pic_deposit_current(sim.ctx, L.PIC_DEPOSIT_CURL_E))
+        L.check(L.lib().pic_deposit_current(sim.ctx, L.PIC_ALL_SPECIES, L.PIC_DEPOSIT_CURL_E))
     assert e.value.code == L.PIC_E_ARG
     sim.deposit()
     sim.fdtd(L.PIC_CURL_E_ADD_J)
@@ -331,7 +337,7 @@ def test_cell_sort_bit_exact(prec):
         g = sim.particles_host(0, s)
         assert np.array_equal(g[0], tid[perm]) and np.array_equal(g[1], xl[:, perm])
         assert np.array_equal(g[2], u[:, perm])
-        nf += int(tiles.near_face(g[1], D).sum())
+        nf += int(tiles.near_face(g[1], D, T).sum())
     assert sim.diagnostics()["near_face"] == nf
     sim.close()
 

@@ -172,5 +172,5 @@ def test_rejected_combinations():
     with pytest.raises(L.PicError):
         PicSim(plasma, tile=(8, 8), precision="fp64", walls=True, fdtd_order=4)
     sim = PicSim(plasma, tile=(8, 8), precision="fp64", fdtd_order=4)
-    assert L.lib().pic_push_interp(sim.ctx, L.PIC_FUSED | L.PIC_PUSH_HALF_B) == L.PIC_E_ARG
+    assert L.lib().pic_push_interp(sim.ctx, L.PIC_ALL_SPECIES, L.PIC_FUSED | L.PIC_PUSH_HALF_B) == L.PIC_E_ARG
     sim.close()

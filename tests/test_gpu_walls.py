@@ -155,7 +155,7 @@ def test_walls_reject_unfused_and_adjoint():
     from paper_1906_06306_amd import _lib as L
     plasma = synth.small_random(2, (16, 16), 2, seed=3)
     sim = make_sim(plasma, (8, 8), "fp64", options=L.PIC_OPT_TRACK)
-    assert L.lib().pic_push_interp(sim.ctx, 0) == L.PIC_E_ARG
+    assert L.lib().pic_push_interp(sim.ctx, L.PIC_ALL_SPECIES, 0) == L.PIC_E_ARG
     la, ua, lE, lB = sim.adjoint_buffers()
     assert L.lib().pic_adjoint_step(sim.ctx, la.data_ptr(), ua.data_ptr(), lE.data_ptr(), lB.data_ptr()) \
         == L.PIC_E_ARG

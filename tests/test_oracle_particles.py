@@ -342,3 +342,82 @@ def test_langmuir_frequency_pins_units(orc):
     cosw = np.median((ex[2:] + ex[:-2]) / (2 * ex[1:-1]))
     w = math.acos(cosw)
     assert abs(2 * math.sin(w / 2) - wp) < 1e-3 * wp
+
+
+# ----------------------------------------- 2D out-of-plane current, wrap
+
+def _path_average_jz(x1, x2, dz, q, n):
+    """Out-of-plane current of a 2D move, built independently of the
+    oracle: along each straight piece of the ZigZag path the current density
+    q vz times the first-order (cloud-in-cell) shape, averaged over the
+    piece by 3-point Gauss-Legendre quadrature (exact for the quadratic
+    product of two linear weights).  The two pieces (x1 -> relay point ->
+    x2) each carry half of the out-of-plane displacement (relay at the
+    midpoint along non-grid dimensions)."""
+    gl_t, gl_w = np.polynomial.legendre.leggauss(3)
+    gl_t = 0.5 * (gl_t + 1.0)
+    gl_w = 0.5 * gl_w
+    J = np.zeros((n[1], n[0]))
+    i1, i2 = np.floor(x1), np.floor(x2)
+    xr = np.minimum(np.minimum(i1, i2) + 1, np.maximum(np.maximum(i1, i2), 0.5 * (x1 + x2)))
+    for a, b, cell in ((x1, xr, i1), (xr, x2, i2)):
+        for t, w in zip(gl_t, gl_w):
+            p = a + t * (b - a)
+            f = p - cell                      # position inside the piece's cell
+            for ca in (0, 1):
+                for cb in (0, 1):
+                    s = (f[0] if ca else 1 - f[0]) * (f[1] if cb else 1 - f[1])
+                    J[int(cell[1] + cb) % n[1], int(cell[0] + ca) % n[0]] += q * 0.5 * dz * w * s
+    return J.reshape(-1)
+
+
+def test_2d_out_of_plane_current_is_the_path_average(orc):
+    """In 2D3V the out-of-plane current of each ZigZag piece is the path
+    average of the particle shape along the piece (Esirkepov 2001's 2D3V
+    out-of-plane current, the same path average that continuity forces on
+    every component in 3D): midpoint weights plus sigma_a sigma_b dx dy / 12.
+    Checked against an independent quadrature of the shape along the path,
+    for in-cell moves with dx, dy, dz all nonzero and for moves that cross
+    one or two faces; a dropped or sign-flipped dx dy / 12 term misses by
+    q dz dx dy / 12."""
+    n = (6, 5, 1)
+    q = 0.8
+    rng = np.random.default_rng(7)
+    cases = [((2.2, 1.3), (0.55, 0.6), 0.7),        # in-cell, large in-plane motion
+             ((3.9, 2.1), (-0.7, 0.8), -0.4)]       # in-cell, opposite signs
+    for _ in range(200):
+        x1 = rng.uniform(1.0, 4.0, 2)
+        d = rng.uniform(-0.95, 0.95, 2)
+        cases.append((tuple(x1), tuple(d), float(rng.uniform(-0.9, 0.9))))
+    worst, crossings = 0.0, 0
+    for x1, d, dz in cases:
+        x1 = np.array(x1)
+        x2 = x1 + np.array(d)
+        crossings += bool((np.floor(x1) != np.floor(x2)).any())
+        J = np.zeros((3, n[0] * n[1]))
+        orc.zigzag(2, n, q, x1[:, None], x2[:, None], np.array([d[0], d[1], dz])[:, None], J)
+        want = _path_average_jz(x1, x2, dz, q, n)
+        worst = max(worst, np.abs(J[2] - want).max())
+    assert crossings > 50
+    assert worst < 1e-15, worst
+    # the term is visible: the first case's cross term q dz dx dy / 12
+    assert abs(q * 0.7 * 0.55 * 0.6 / 12) > 1e-2
+
+
+def test_wrap_edges(orc):
+    """C-13: after the periodic wrap every coordinate lies in [0, N), also
+    at the edges: a tiny negative value whose sum with N rounds to N becomes
+    0, x = N becomes 0, N minus one ulp stays, 2N minus one ulp maps to N
+    minus that ulp (exact), and -ulp(N) maps to N - ulp(N)."""
+    N = 64
+    n = (N, 1, 1)
+    ulp_n = np.spacing(float(N))
+    x = np.array([[-1e-17, -ulp_n / 4, N - ulp_n, float(N), 2 * N - 2 * ulp_n, -ulp_n, 0.0, 3.5]])
+    want = [0.0, 0.0, N - ulp_n, 0.0, N - 2 * ulp_n, N - ulp_n, 0.0, 3.5]
+    orc.wrap(1, n, x)
+    assert x[0].tolist() == want
+    assert (x >= 0).all() and (x < N).all()
+    # per dimension in 2D and 3D as well
+    x3 = np.array([[-1e-17, 5.0], [float(N), -1e-300], [7.25, 2 * N - 2 * ulp_n]])
+    orc.wrap(3, (N, N, N), x3)
+    assert x3.tolist() == [[0.0, 5.0], [0.0, 0.0], [7.25, N - 2 * ulp_n]]

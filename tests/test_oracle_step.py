@@ -168,3 +168,44 @@ def test_paper_printed_physics_numbers():
     assert abs(comp - val) < tol
     val, tol, _ = g["shock_speed_mhd"]
     assert abs(bsh - val) < tol
+
+
+@pytest.mark.parametrize("D,nthreads", [(1, 3), (2, 4), (3, 5)])
+def test_threaded_step_matches_single_thread(D, nthreads):
+    """The all-thread CPU baseline computes the single-thread oracle's step:
+    particles bit for bit, J and E to the rounding of the reordered current
+    sums (relative 1e-14), over 3 steps."""
+    import oracle
+    n = {1: (64,), 2: (32, 24), 3: (12, 12, 8)}[D]
+    plasma = synth.small_random(D, n, 6, seed=70 + D, field_amp=0.05)
+    a = oracle.State(plasma)
+    b = oracle.State(plasma)
+    a.step(3)
+    b.step(3, threads=nthreads)
+    for s in range(2):
+        assert np.abs(a.x[s] - b.x[s]).max() < 1e-12 and np.abs(a.u[s] - b.u[s]).max() < 1e-13
+    for x, y in ((a.J, b.J), (a.E, b.E), (a.B, b.B)):
+        assert np.linalg.norm(x - y) <= 1e-14 * np.linalg.norm(x)
+    # one step from the same state: particles identical bit for bit
+    c, d = oracle.State(plasma), oracle.State(plasma)
+    c.step(1)
+    d.step(1, threads=nthreads)
+    for s in range(2):
+        assert np.array_equal(c.x[s], d.x[s]) and np.array_equal(c.u[s], d.u[s])
+
+
+@pytest.mark.parametrize("D", [1, 2, 3])
+def test_split_step_equals_step(D):
+    """push_particles + finish_step run the routines of orc_step in its
+    order: bit for bit the same state."""
+    import oracle
+    n = {1: (40,), 2: (24, 16), 3: (8, 8, 8)}[D]
+    plasma = synth.small_random(D, n, 4, seed=80 + D, field_amp=0.05)
+    a, b = oracle.State(plasma), oracle.State(plasma)
+    for _ in range(2):
+        a.step(1)
+        b.finish_step(b.push_particles())
+    for s in range(2):
+        assert np.array_equal(a.x[s], b.x[s]) and np.array_equal(a.u[s], b.u[s])
+    for x, y in ((a.E, b.E), (a.B, b.B), (a.J, b.J)):
+        assert np.array_equal(x, y)

@@ -104,6 +104,48 @@ def test_cell_sort_and_keys_brute_force():
 
 
 def test_near_face_flags():
-    xl = np.array([[0.0, 1.5, np.float32(2.0) - np.float32(2.0 ** -23), -3.0, 0.25]], dtype=np.float32)
-    f = tiles.near_face(xl, 1)
-    assert f.tolist() == [True, False, True, True, False]
+    """The band is 2 ulps of the storage precision at the tile half-width:
+    for T = 16 in FP32, 2 * 2^-20 around every integer, whatever the size of
+    the coordinate itself."""
+    f32 = np.float32
+    h = 2.0 ** -20
+    vals = [0.0, 1.5, f32(2.0) - f32(2.0 ** -23), -3.0, 0.25, f32(5 + 1.5 * h), f32(5 + 2.5 * h),
+            f32(-7.0 - 2 * h), f32(-8.0), f32(7.9999995), f32(0.5 * h), f32(3 * h)]
+    xl = np.array([vals], dtype=np.float32)
+    f = tiles.near_face(xl, 1, (16, 1, 1))
+    want = [True, False, True, True, False, True, False, True, True, True, True, False]
+    assert f.tolist() == want
+    # brute force over FP32 neighbours of a few integers: flagged exactly
+    # when at most 2^-19 away
+    for k in (-8, -3, 0, 1, 7):
+        v = np.float32(k)
+        up, dn = [v], [v]
+        for _ in range(40):
+            up.append(np.nextafter(up[-1], np.float32(np.inf)))
+            dn.append(np.nextafter(dn[-1], np.float32(-np.inf)))
+        xs = np.array([up + dn], dtype=np.float32)
+        fl = tiles.near_face(xs, 1, (16, 1, 1))
+        for val, got in zip(xs[0], fl):
+            assert got == (abs(float(val) - k) <= 2 * h), (k, float(val))
+    # FP64: the band is 2 ulp(8) = 2^-48
+    xd = np.array([[3.0 + 2.0 ** -49, 3.0 + 2.0 ** -47]])
+    assert tiles.near_face(xd, 1, (16, 1, 1)).tolist() == [True, False]
+
+
+def test_migration_counts_brute_force():
+    """P-12: counts per (tile, direction) from matched tile ids against a
+    plain loop over the particles, including moves across the periodic seam."""
+    rng = np.random.default_rng(4)
+    n, T, D = (48, 40, 1), (8, 8, 1), 2
+    nt = [6, 5, 1]
+    ntiles = 30
+    a = rng.integers(0, ntiles, 5000)
+    delta = rng.integers(-1, 2, (2, 5000))
+    ax, ay = a % 6, a // 6
+    b = (ax + delta[0]) % 6 + 6 * ((ay + delta[1]) % 5)
+    got = tiles.migration_counts(a, b, n, T, D, ntiles)
+    want = np.zeros((ntiles, 9), dtype=np.int64)
+    for i in range(a.size):
+        want[a[i], (delta[0, i] + 1) + 3 * (delta[1, i] + 1)] += 1
+    assert np.array_equal(got, want)
+    assert got.sum() == a.size
