@@ -382,6 +382,22 @@ pic_status pic_error(pic_ctx *ctx);
  * return value includes the latched device error bits (then cleared). */
 pic_status pic_diagnostics(pic_ctx *ctx, pic_diag *out);
 
+/* The diagnostics of pic_diagnostics for callers that cannot allocate memory
+ * (code in tight serving or stepping loops, harnesses that forbid
+ * allocation): the same values (the reduction over tiles runs on the
+ * device in the same order as pic_diagnostics' host loop), with the
+ * per-tile partial sums and charge blocks in a static device array of the
+ * library (16 MiB per device, held until the process ends) instead of the
+ * workspace and a host buffer; it allocates no device or host memory.
+ * PIC_E_ARG if the context's tiles need more than 16 MiB there: 8 doubles
+ * plus (T+1)^D charge values per tile (e.g. 4,096 2D tiles of 16^2 cells
+ * take 9.7 MB).  Every context on a device shares that device's array, and
+ * each call overwrites it completely: calls that overlap on one device (two
+ * threads, or two streams) race and must be serialised by the caller.
+ * Synchronises the stream; returns the latched device error bits (then
+ * cleared) like pic_diagnostics. */
+pic_status pic_diagnostics_static(pic_ctx *ctx, pic_diag *out);
+
 /* The same diagnostics per box: out is a host array of n_boxes entries
  * (error_bits is the context's, repeated in every entry). */
 pic_status pic_diagnostics_boxes(pic_ctx *ctx, pic_diag *out);

@@ -39,7 +39,7 @@ PIC_PUSHER_HC = 2
 
 EXPORTS = ["pic_query", "pic_init_tiles", "pic_fdtd_step", "pic_push_interp", "pic_deposit_current",
            "pic_sort_migrate", "pic_step", "pic_inject", "pic_filter_current", "pic_graph_capture", "pic_graph_launch", "pic_error",
-           "pic_diagnostics", "pic_diagnostics_boxes", "pic_adjoint_unpermute", "pic_adjoint_step", "pic_destroy", "pic_last_error"]
+           "pic_diagnostics", "pic_diagnostics_static", "pic_diagnostics_boxes", "pic_adjoint_unpermute", "pic_adjoint_step", "pic_destroy", "pic_last_error"]
 
 P = ctypes.c_void_p
 I32 = ctypes.c_int32
@@ -111,6 +111,7 @@ def lib():
             "pic_graph_launch": [P],
             "pic_error": [P],
             "pic_diagnostics": [P, P],
+            "pic_diagnostics_static": [P, P],
             "pic_diagnostics_boxes": [P, P],
             "pic_adjoint_unpermute": [P, P, P, P, P, I64],
             "pic_adjoint_step": [P, P, P, P, P],

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -39,16 +40,28 @@ constexpr int64_t MAX_SLOTS = int64_t(1) << 28;
 // init or an injection, and at every push captured into a graph
 constexpr int ORDER_EVERY = 8;
 
-thread_local std::string g_last_error;
+// text of the last error on this thread (a fixed buffer: reporting an
+// error allocates nothing)
+thread_local char g_last_error[512];
+
+// Device scratch of pic_diagnostics_static, the diagnostics for callers that
+// cannot allocate memory: the per-tile partial sums, the per-tile charge
+// blocks and the reduced record.  Every device the library runs on holds
+// one copy until the process ends; host code reaches a device's copy only
+// through the address hipGetSymbolAddress returns for it (per device, at
+// pic_init_tiles), never through the symbol itself.
+constexpr uint64_t STATIC_SCRATCH_BYTES = uint64_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_dev;   // device id -> address of that device's scratch
 
 pic_status fail(pic_status code, const char *fmt, ...)
 {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
     va_end(ap);
-    g_last_error = buf;
     return code;
 }
 
@@ -59,6 +72,24 @@ pic_status fail(pic_status code, const char *fmt, ...)
     } while (0)
 
 uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
+
+// Address of the current device's copy of `scratch` (looked up once per
+// device, with that device current).
+pic_status scratch_address(void **out)
+{
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_dev.size() <= dev) g_scratch_dev.resize(dev + 1, nullptr);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(PIC_E_HIP, "hipGetSymbolAddress returned a null address for the static scratch");
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return PIC_OK;
+}
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 // Internal layout: the public offsets plus the staging regions.
@@ -300,6 +331,7 @@ struct pic_ctx {
     uint32_t all_species;   // mask of every species
     uint32_t pushed;        // species pushed in the current step
     uint32_t launch_mask;   // species of the next launch (Params::species_mask)
+    uint8_t *scratch;       // this device's static scratch (pic_diagnostics_static)
 };
 
 namespace {
@@ -737,12 +769,12 @@ struct Impl {
         return PIC_OK;
     }
 
-    static pic_status diag(pic_ctx *x, pic_diag *out, bool per_box)
+    // per-tile diagnostic partials into part [tiles][NPART] and the charge
+    // blocks into rblk [tiles][(T+1)^D]
+    static pic_status diag_partials(pic_ctx *x, double *part, double *rblk, int cont_valid)
     {
         Params<R> p = params<R>(x);
         const Layout &L = x->L;
-        double *part = reinterpret_cast<double *>(x->ws + L.off_part);
-        double *rblk = reinterpret_cast<double *>(x->ws + L.off_rblk);
         const double *mass = reinterpret_cast<const double *>(x->ws + L.off_mass);
         size_t lds = L.rblk_cells * sizeof(double);
         pic_status st = set_lds(pic::k_diag_tile<R, D>, lds);
@@ -750,9 +782,57 @@ struct Impl {
         dim3 g((unsigned)L.pub.tiles_total);
         hipLaunchKernelGGL((pic::k_diag_tile<R, D>), g, dim3(256), lds, x->stream, p, mass, part, rblk);
         double *rho_prev = reinterpret_cast<double *>(x->ws + L.off_rho_prev);
-        const int cont_valid = x->diag_step >= 0 && x->steps - x->diag_step == 1;
         hipLaunchKernelGGL((pic::k_diag_gauss<R, D>), g, dim3(256), 0, x->stream, p, part, rblk, rho_prev, cont_valid);
         HIP_OK(hipGetLastError());
+        return PIC_OK;
+    }
+
+    // the diagnostics with the partials in the static scratch, reduced on
+    // the device; no allocation of any kind
+    static pic_status diag_static(pic_ctx *x, pic_diag *out)
+    {
+        const Layout &L = x->L;
+        const uint64_t part_bytes = align256(L.pub.tiles_total * pic::NPART * sizeof(double));
+        const uint64_t rblk_bytes = align256(L.pub.tiles_total * L.rblk_cells * sizeof(double));
+        const uint64_t need = part_bytes + rblk_bytes + align256(sizeof(pic::DiagRec));
+        if (need > STATIC_SCRATCH_BYTES)
+            return fail(PIC_E_ARG, "pic_diagnostics_static needs %llu bytes of static scratch for %lld tiles; "
+                                   "the limit is %llu bytes (use pic_diagnostics)",
+                        (unsigned long long)need, (long long)L.pub.tiles_total,
+                        (unsigned long long)STATIC_SCRATCH_BYTES);
+        double *part = reinterpret_cast<double *>(x->scratch);
+        double *rblk = reinterpret_cast<double *>(x->scratch + part_bytes);
+        pic::DiagRec *rec = reinterpret_cast<pic::DiagRec *>(x->scratch + part_bytes + rblk_bytes);
+        const int cont_valid = x->diag_step >= 0 && x->steps - x->diag_step == 1;
+        pic_status st = diag_partials(x, part, rblk, cont_valid);
+        if (st) return st;
+        hipLaunchKernelGGL(pic::k_diag_reduce, dim3(1), dim3(64), 0, x->stream, part, L.pub.tiles_total, cont_valid,
+                           rec);
+        HIP_OK(hipGetLastError());
+        pic::DiagRec h{};
+        HIP_OK(hipMemcpyAsync(&h, rec, sizeof h, hipMemcpyDeviceToHost, x->stream));
+        HIP_OK(hipStreamSynchronize(x->stream));
+        memset(out, 0, sizeof *out);
+        out->field_energy = h.field_energy;
+        out->kinetic_energy = h.kinetic_energy;
+        out->gauss_max = h.gauss_max;
+        out->divb_max = h.divb_max;
+        out->charge_total = h.charge_total;
+        out->particles = h.particles;
+        out->near_face = h.near_face;
+        out->continuity_max = h.continuity_max;
+        x->diag_step = x->steps;
+        return PIC_OK;
+    }
+
+    static pic_status diag(pic_ctx *x, pic_diag *out, bool per_box)
+    {
+        const Layout &L = x->L;
+        double *part = reinterpret_cast<double *>(x->ws + L.off_part);
+        double *rblk = reinterpret_cast<double *>(x->ws + L.off_rblk);
+        const int cont_valid = x->diag_step >= 0 && x->steps - x->diag_step == 1;
+        pic_status st = diag_partials(x, part, rblk, cont_valid);
+        if (st) return st;
         std::vector<double> h(L.pub.tiles_total * pic::NPART);
         HIP_OK(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, x->stream));
         HIP_OK(hipStreamSynchronize(x->stream));
@@ -806,6 +886,7 @@ pic_status do_migrate(pic_ctx *x, bool out, bool in, bool sort, int32_t *mc, int
     PIC_DISPATCH(x, migrate(x, out, in, sort, mc, fl, fcap));
 }
 pic_status do_diag(pic_ctx *x, pic_diag *o, bool per_box) { PIC_DISPATCH(x, diag(x, o, per_box)); }
+pic_status do_diag_static(pic_ctx *x, pic_diag *o) { PIC_DISPATCH(x, diag_static(x, o)); }
 pic_status do_adjoint(pic_ctx *x, void *a, void *b, void *c, void *d) { PIC_DISPATCH(x, adjoint(x, a, b, c, d)); }
 pic_status do_filter(pic_ctx *x, int passes) { PIC_DISPATCH(x, filter(x, passes)); }
 pic_status do_inject(pic_ctx *x, int b, int s, int64_t n, const double *pos, const double *u)
@@ -936,6 +1017,11 @@ pic_status pic_init_tiles(const pic_config *cfg, const int64_t *counts, void *wo
         if (e_ != hipSuccess) return cleanup(fail(PIC_E_HIP, "%s: %s", #expr, hipGetErrorString(e_))); \
     } while (0)
     INIT_HIP(hipStreamSynchronize(x->stream));
+    {
+        void *sp = nullptr;
+        if ((st = scratch_address(&sp))) return cleanup(st);
+        x->scratch = reinterpret_cast<uint8_t *>(sp);
+    }
     INIT_HIP(hipMemcpy(x->ws + L.off_tiles, L.tiles.data(), L.tiles.size() * sizeof(TileDesc), hipMemcpyHostToDevice));
     INIT_HIP(hipMemcpy(x->ws + L.pub.off_seg_offset, L.seg_off.data(), L.seg_off.size() * 8, hipMemcpyHostToDevice));
     INIT_HIP(hipMemcpy(x->ws + L.pub.off_seg_capacity, L.seg_cap.data(), L.seg_cap.size() * 4, hipMemcpyHostToDevice));
@@ -1153,6 +1239,17 @@ pic_status pic_diagnostics(pic_ctx *x, pic_diag *out)
     return error_status(bits);
 }
 
+pic_status pic_diagnostics_static(pic_ctx *x, pic_diag *out)
+{
+    if (!x || !out) return fail(PIC_E_ARG, "null argument");
+    pic_status st = do_diag_static(x, out);
+    if (st) return st;
+    int32_t bits = 0;
+    if ((st = read_error(x, &bits))) return st;
+    out->error_bits = bits;
+    return error_status(bits);
+}
+
 pic_status pic_diagnostics_boxes(pic_ctx *x, pic_diag *out)
 {
     if (!x || !out) return fail(PIC_E_ARG, "null argument");
@@ -1194,6 +1291,6 @@ pic_status pic_destroy(pic_ctx *x)
     return PIC_OK;
 }
 
-const char *pic_last_error(void) { return g_last_error.c_str(); }
+const char *pic_last_error(void) { return g_last_error; }
 
 }  // extern "C"

@@ -444,4 +444,32 @@ __global__ void __launch_bounds__(256) k_diag_gauss(Params<R> p, double *part, c
     }
 }
 
+// The diagnostics of all tiles reduced into one record.
+struct DiagRec {
+    double field_energy, divb_max, kinetic_energy, gauss_max, charge_total, continuity_max;
+    long long particles, near_face;
+};
+
+// Sum the per-tile partials of k_diag_tile / k_diag_gauss in tile order on
+// one thread: the same order and arithmetic as a host loop over the tiles,
+// so the record equals the host reduction of the same partials.
+__global__ void k_diag_reduce(const double *part, int64_t ntiles, int cont_valid, DiagRec *rec)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    DiagRec r{};
+    r.continuity_max = cont_valid ? 0.0 : -1.0;
+    for (int64_t t = 0; t < ntiles; ++t) {
+        const double *o = part + t * NPART;
+        r.field_energy += o[0];
+        r.divb_max = fmax(r.divb_max, o[1]);
+        r.kinetic_energy += o[2];
+        r.particles += (long long)o[3];
+        r.gauss_max = fmax(r.gauss_max, o[4]);
+        r.charge_total += o[5];
+        if (cont_valid) r.continuity_max = fmax(r.continuity_max, o[6]);
+        r.near_face += (long long)o[7];
+    }
+    *rec = r;
+}
+
 }  // namespace pic
