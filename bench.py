@@ -222,9 +222,9 @@ def cpu_oracle_rate(plasma, steps, threads=1):
     return plasma.nparticles * steps / dt, dt, first
 
 
-def common_state_error(plasma, precision, tile, block):
-    """One GPU step from the GPU's own binned state against the oracle's
-    step from that state widened to FP64 (whole lattice).  Where the two put
+def common_state_error(plasma, precision, tile, block, warm=5):
+    """One GPU step from the GPU's own state after `warm` steps against the
+    oracle's step from that state widened to FP64 (whole lattice).  Where the two put
     a particle's end point in different cells (an end point within rounding
     of a face), the oracle deposits from the kernel's end point, so both take
     that integer decision in the kernel's precision; those particles are
@@ -239,6 +239,7 @@ def common_state_error(plasma, precision, tile, block):
     n0 = dims[0]
     sim = PicSim(plasma, tile=(tile, tile), precision=precision, block=block, capacity_factor=3.0,
                  options=L.PIC_OPT_TRACK)
+    sim.step(warm, fused=True, half_b_in_push=True)
 
     def slots(s):
         _, _, _, off, cnt = sim.particle_views()
@@ -279,6 +280,7 @@ def common_state_error(plasma, precision, tile, block):
     out["end_cells_taken_from_kernel"] = realigned
     out["of_them_unflagged"] = unflagged
     out["near_face_flagged"] = int(total)
+    out["after_steps"] = warm
     sim.close()
     del sim
     torch.cuda.empty_cache()

@@ -153,17 +153,18 @@ __device__ __forceinline__ void latch_wave(int32_t *err, int32_t bits)
 // LDS atomic add of a current value computed in precision R into an
 // accumulator of type A.  A = float or double: a floating-point add.
 // A = long long (FP32 runs): fixed point.  The deposit's charge is scaled by
-// 2^e (fixed_exponent) so that every ZigZag value has magnitude below 2^31;
-// the value is rounded to the nearest integer (an error of at most 2^-31 of
-// the largest value, far below FP32 rounding) and added exactly, so a block
-// does not depend on the order of its atomics, and the 64-bit integer add of
-// the LDS runs much faster than its FP64 add on gfx950.
+// 2^e (fixed_exponent, |q| 2^e in [2^29, 2^30)) so that every ZigZag value
+// has magnitude below 2^31; the value is truncated to an integer (an error
+// below one unit, 2^-29 |q|, under the FP32 rounding of a value of a tenth
+// of |q|) and added exactly, so a block does not depend on the order of its
+// atomics, and the 64-bit integer add of the LDS runs much faster than its
+// FP64 add on gfx950.
 template <typename A, typename R>
 __device__ __forceinline__ void lds_add(A *p, R v)
 {
     if constexpr (std::is_same<A, long long>::value) {
         static_assert(sizeof(R) == 4, "fixed-point accumulation is for FP32 values");
-        atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)(long long)__float2int_rn(v));
+        atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)(long long)(int)v);
     } else {
         atomicAdd(p, (A)v);
     }
@@ -453,6 +454,18 @@ __device__ __forceinline__ void displacement(const R u[3], R c, R dv[3])
     dv[2] = u[2] * r;
 }
 
+// The same, returning gamma^2 = 1 + |u|^2 (finite exactly when u is).
+template <typename R>
+__device__ __forceinline__ R displacement_sq(const R u[3], R c, R dv[3])
+{
+    const R g2 = R(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const R r = c * rsqrt_w<R>(g2);
+    dv[0] = u[0] * r;
+    dv[1] = u[1] * r;
+    dv[2] = u[2] * r;
+    return g2;
+}
+
 // ----------------------------------------------------------------- ZigZag
 
 // Current of one straight segment inside one cell, as the values it adds
@@ -505,6 +518,52 @@ __device__ __forceinline__ void segment_values(const R F[3], const R W[3], const
     }
 }
 
+// The same values as flux component times weight: value k is
+// F[seg_comp<D>(k)] * wt[k].
+template <int D>
+__host__ __device__ constexpr int seg_comp(int k)
+{
+    return D == 1 ? (k == 0 ? 0 : (k < 3 ? 1 : 2)) : (D == 2 ? (k < 2 ? 0 : (k < 4 ? 1 : 2)) : (k < 4 ? 0 : (k < 8 ? 1 : 2)));
+}
+
+template <typename R, int D>
+__device__ __forceinline__ void segment_weights(const R W[3], const R dv[3], R wt[seg_values<D>()])
+{
+    if constexpr (D == 1) {
+        wt[0] = R(1);
+        wt[1] = R(1) - W[0];
+        wt[2] = W[0];
+        wt[3] = R(1) - W[0];
+        wt[4] = W[0];
+    } else if constexpr (D == 2) {
+        wt[0] = R(1) - W[1];
+        wt[1] = W[1];
+        wt[2] = R(1) - W[0];
+        wt[3] = W[0];
+        const R cr = dv[0] * dv[1] * R(1.0 / 12.0);
+        wt[4] = (R(1) - W[0]) * (R(1) - W[1]) + cr;
+        wt[5] = W[0] * (R(1) - W[1]) - cr;
+        wt[6] = (R(1) - W[0]) * W[1] - cr;
+        wt[7] = W[0] * W[1] + cr;
+    } else {
+        const R cyz = dv[1] * dv[2] * R(1.0 / 12.0);
+        wt[0] = (R(1) - W[1]) * (R(1) - W[2]) + cyz;
+        wt[1] = W[1] * (R(1) - W[2]) - cyz;
+        wt[2] = (R(1) - W[1]) * W[2] - cyz;
+        wt[3] = W[1] * W[2] + cyz;
+        const R cxz = dv[0] * dv[2] * R(1.0 / 12.0);
+        wt[4] = (R(1) - W[0]) * (R(1) - W[2]) + cxz;
+        wt[5] = W[0] * (R(1) - W[2]) - cxz;
+        wt[6] = (R(1) - W[0]) * W[2] - cxz;
+        wt[7] = W[0] * W[2] + cxz;
+        const R cxy = dv[0] * dv[1] * R(1.0 / 12.0);
+        wt[8] = (R(1) - W[0]) * (R(1) - W[1]) + cxy;
+        wt[9] = W[0] * (R(1) - W[1]) - cxy;
+        wt[10] = (R(1) - W[0]) * W[1] - cxy;
+        wt[11] = W[0] * W[1] + cxy;
+    }
+}
+
 // LDS offsets (relative to the segment's cell) of those values: component
 // plane offset plus corner offset.
 template <int D>
@@ -547,7 +606,8 @@ __device__ __forceinline__ int seg_offset(const CurBox<D> &cb, int k)
 // Relay point per grid dimension: min(min(i1,i2)+1, max(max(i1,i2),
 // (x1+x2)/2)); along non-grid dimensions the two segments share dv/2.
 // When both segments lie in the same cell they touch the same points, so
-// their values are added in registers and written with one set of atomics.
+// their values are added in registers (F1 w1 + F2 w2, one multiply-add) and
+// written with one set of atomics.
 template <typename R, int D, typename A>
 __device__ __forceinline__ void zigzag(A *sJ, const CurBox<D> &cb, const int32_t T[3], const R x1[3], const R x2[3],
                                        const R dv[3], R q)
@@ -580,17 +640,22 @@ __device__ __forceinline__ void zigzag(A *sJ, const CurBox<D> &cb, const int32_t
         }
     }
     constexpr int NV = seg_values<D>();
-    R v1[NV], v2[NV];
-    segment_values<R, D>(F1, W1, d1, v1);
-    segment_values<R, D>(F2, W2, d2, v2);
+    R w1[NV], w2[NV], F2s[3];
+    segment_weights<R, D>(W1, d1, w1);
+    segment_weights<R, D>(W2, d2, w2);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) F2s[d] = same ? F2[d] : R(0);
     const int s1 = cb.e0, s2 = cb.e0 * cb.e1;
     const int b1 = l1[0] + (D > 1 ? imul24(l1[1], s1) : 0) + (D > 2 ? imul24(l1[2], s2) : 0);
 #pragma unroll
-    for (int k = 0; k < NV; ++k) lds_add(sJ + b1 + seg_offset<D>(cb, k), same ? v1[k] + v2[k] : v1[k]);
+    for (int k = 0; k < NV; ++k) {
+        const int m = seg_comp<D>(k);
+        lds_add(sJ + b1 + seg_offset<D>(cb, k), fma(F2s[m], w2[k], F1[m] * w1[k]));
+    }
     if (!same) {
         const int b2 = l2[0] + (D > 1 ? imul24(l2[1], s1) : 0) + (D > 2 ? imul24(l2[2], s2) : 0);
 #pragma unroll
-        for (int k = 0; k < NV; ++k) lds_add(sJ + b2 + seg_offset<D>(cb, k), v2[k]);
+        for (int k = 0; k < NV; ++k) lds_add(sJ + b2 + seg_offset<D>(cb, k), F2[seg_comp<D>(k)] * w2[k]);
     }
 }
 

@@ -11,11 +11,36 @@ namespace pic {
 
 constexpr int MAX_WAVES = 16;
 
-// groups of particles the push loads ahead of the one it works on (2 and 3
-// measured no faster than 1 on the 2D FP32 and FP64 push and cost registers)
-#ifndef PUSH_PREFETCH
-#define PUSH_PREFETCH 1
-#endif
+// groups of particles the push loads ahead of the one it works on: one.  A
+// second group in flight (in registers, or in a second buffer of registers
+// the loop alternates) measured slower on the 2D FP32 push: the compiler's
+// waits for the alternate buffer come back, and the registers lower occupancy.
+constexpr int PUSH_PREFETCH = 1;
+
+// Inclusive prefix sum of v over each row of 16 lanes (DPP row shifts; a
+// shifted-in lane outside the row reads 0).  Lanes 0..15 hold the prefix of
+// lanes 0..15.
+__device__ __forceinline__ int row_prefix16(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);   // row_shr:8
+    return v;
+}
+
+// The per-wave totals of a work-group scan (written by lane 0 of every wave
+// to tot[wave], before a barrier): returns the sum over the waves below this
+// one and, in all, over every wave.  Lane w reads the total of wave w and the
+// first 16 lanes scan them, so the cost does not grow with the wave count.
+__device__ __forceinline__ int wave_totals(const int *tot, int wave, int nw, int &all)
+{
+    const int lane = threadIdx.x & 63;
+    const int v = lane < nw ? tot[lane & (MAX_WAVES - 1)] : 0;
+    const int incl = row_prefix16(v);
+    all = __builtin_amdgcn_readlane(incl, nw - 1);
+    return __builtin_amdgcn_readlane(incl - v, wave);
+}
 
 // Exclusive prefix of a per-thread flag over the whole work-group (wave
 // ballots, then per-wave totals in LDS).  sTot holds 2*MAX_WAVES ints and the
@@ -23,8 +48,7 @@ constexpr int MAX_WAVES = 16;
 __device__ __forceinline__ int wg_scan_flag(bool flag, int *sTot, int parity, int &total)
 {
     const int lane = threadIdx.x & 63;
-    // the wave index, wave count and per-wave totals are uniform: keep them
-    // scalar (unrolled over the largest wave count, immediate LDS offsets)
+    // the wave index and wave count are uniform (scalar registers)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nw = __builtin_amdgcn_readfirstlane(blockDim.x >> 6);
     unsigned long long m = __ballot(flag);
@@ -32,16 +56,7 @@ __device__ __forceinline__ int wg_scan_flag(bool flag, int *sTot, int parity, in
     int *tot = sTot + parity * MAX_WAVES;
     if (lane == 0) tot[wave] = __popcll(m);
     __syncthreads();
-    int off = 0, all = 0;
-#pragma unroll
-    for (int w = 0; w < MAX_WAVES; ++w) {
-        if (w < nw) {
-            const int v = __builtin_amdgcn_readfirstlane(tot[w]);
-            off += w < wave ? v : 0;
-            all += v;
-        }
-    }
-    total = all;
+    const int off = wave_totals(tot, wave, nw, total);
     return off + below;
 }
 
@@ -52,8 +67,7 @@ template <int U>
 __device__ __forceinline__ int wg_scan_flags(const bool f[U], int *sTot, int parity, int pre[U])
 {
     const int lane = threadIdx.x & 63;
-    // the wave index, wave count and per-wave totals are uniform: keep them
-    // scalar (unrolled over the largest wave count, immediate LDS offsets)
+    // the wave index and wave count are uniform (scalar registers)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nw = __builtin_amdgcn_readfirstlane(blockDim.x >> 6);
     int *tot = sTot + parity * U * MAX_WAVES;
@@ -68,16 +82,10 @@ __device__ __forceinline__ int wg_scan_flags(const bool f[U], int *sTot, int par
     int run = 0;
 #pragma unroll
     for (int j = 0; j < U; ++j) {
-        int base = 0;
-#pragma unroll
-        for (int w = 0; w < MAX_WAVES; ++w) {
-            if (w < nw) {
-                const int v = __builtin_amdgcn_readfirstlane(tot[j * MAX_WAVES + w]);
-                base = w == wave ? run : base;
-                run += v;
-            }
-        }
-        pre[j] = base + below[j];
+        int all;
+        const int off = wave_totals(tot + j * MAX_WAVES, wave, nw, all);
+        pre[j] = run + off + below[j];
+        run += all;
     }
     return run;
 }
@@ -245,6 +253,43 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int w, unsig
         }
         int32_t *const OD = p.ob_dir + (int64_t)ts * p.ob_dir_stride;
         int keep = 0, nleave = 0;
+        // The fused push writes a group's particles at the top of the next
+        // iteration, before that iteration's prefetch.  The vector-memory
+        // counter retires loads and stores in issue order, and a group's
+        // stores depend on the lane masks (stayers, leavers): a wait for the
+        // prefetched group would otherwise also wait for the stores issued just
+        // before it.  Issued first, they complete under the next group's
+        // compute.  (Stores go to compacted slots below the group just read,
+        // and the prefetch reads beyond it.)
+        struct Pending {
+            bool stay, leave;
+            uint32_t off;          // byte offset of the compacted or outbox slot
+            int code;
+            int32_t origin;
+            R x2[3], u[3];
+        } pend[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) pend[j].stay = pend[j].leave = false;
+        auto flush_pending = [&]() {
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                if (pend[j].stay) {
+#pragma unroll
+                    for (int d = 0; d < D; ++d) st_off(X[d], pend[j].off, pend[j].x2[d]);
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) st_off(V[m], pend[j].off, pend[j].u[m]);
+                    if (p.ids) st_off(p.ids + so, pend[j].off / (uint32_t)sizeof(R) * 4u, pend[j].origin);
+                } else if (pend[j].leave) {
+#pragma unroll
+                    for (int d = 0; d < D; ++d) st_off(OX[d], pend[j].off, pend[j].x2[d]);
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) st_off(OU[m], pend[j].off, pend[j].u[m]);
+                    const uint32_t o4 = pend[j].off / (uint32_t)sizeof(R) * 4u;
+                    st_off(OD, o4, pend[j].code);
+                    if (p.ids) st_off(p.ob_ids + ob, o4, pend[j].origin);
+                }
+            }
+        };
         // the particles of the next PF groups, loaded PF groups ahead.
         // Segment capacities are multiples of the group size, so every lane
         // of a group indexes a slot of the segment (lanes past the count read
@@ -288,6 +333,13 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int w, unsig
                         nx[g][j][d] = nx[g + 1][j][d];
                         nu[g][j][d] = nu[g + 1][j][d];
                     }
+            if constexpr (FUSED) {
+                // wait for this group's particles (and the stores issued with
+                // them, a group ago) before issuing the previous group's
+                // stores: s_waitcnt vmcnt(0), other counters untouched
+                __builtin_amdgcn_s_waitcnt(0x0F70);
+                flush_pending();                       // the previous group's stores
+            }
             // prefetch: later groups lie beyond every element this group
             // writes (compaction only moves elements down)
             if (c0 + PF * G < cnt) {
@@ -311,10 +363,14 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int w, unsig
                     R e[3], b[3], dv[3];
                     interp_all<R, D>(sE, cb, sB, fb, x[j], T, e, b);
                     push_u<R, PUSHER>(u[j], e, b, c, inv_c, sq);
-                    displacement<R>(u[j], c, dv);
+                    const R usq = displacement_sq<R>(u[j], c, dv);
 #pragma unroll
                     for (int d = 0; d < D; ++d) x2[j][d] = x[j][d] + dv[d];
-                    if (finite3<R>(u[j]) && moved_ok<R, D>(x2[j], dv, T)) {
+                    // for finite momenta |dv_d| < c <= 1/sqrt(D), so the end point
+                    // stays in the current halo; 1 + |u|^2 is finite exactly when
+                    // u is.  Only a Courant number close to 1 (1D) can round a
+                    // displacement to a whole cell: then every move is checked.
+                    if (isfinite(usq) && (c < R(0.99) || moved_ok<R, D>(x2[j], dv, T))) {
                         if constexpr (FUSED) {
                             bool done = false;
                             if constexpr (WALLS) done = wall_reflect<R, D, A>(sJ, cb, T, td.walls, x[j], x2[j], u[j], dv, qd);
@@ -322,7 +378,7 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int w, unsig
                             code[j] = direction_code<R, D>(x2[j], T, delta[j]);
                         }
                     } else {
-                        errs |= finite3<R>(u[j]) ? ERR_CFL : ERR_NONFINITE;
+                        errs |= isfinite(usq) ? ERR_CFL : ERR_NONFINITE;
 #pragma unroll
                         for (int d = 0; d < D; ++d) x2[j][d] = x[j][d];
                     }
@@ -348,31 +404,29 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int w, unsig
 #pragma unroll
                 for (int j = 0; j < U; ++j) {
                     // stayers to their compacted slot, leavers to the outbox
-                    // (the two store sets run under complementary lane masks;
-                    // lanes past the count store nothing)
+                    // rebased (written at the top of the next iteration, under
+                    // complementary lane masks; lanes past the count write
+                    // nothing)
                     const int lane_idx = j * (int)blockDim.x + (int)threadIdx.x;
-                    const int32_t origin = (int32_t)(so + c0 + lane_idx);   // slot read from
+                    pend[j].origin = (int32_t)(so + c0 + lane_idx);   // slot read from
+                    pend[j].stay = stay[j];
+                    pend[j].leave = !stay[j] && valid[j];
+                    pend[j].code = code[j];
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) pend[j].u[m] = u[j][m];
                     if (stay[j]) {
-                        const uint32_t k = (uint32_t)(keep + pre[j]);
-                        const uint32_t o = k * (uint32_t)sizeof(R);
+                        pend[j].off = (uint32_t)(keep + pre[j]) * (uint32_t)sizeof(R);
 #pragma unroll
-                        for (int d = 0; d < D; ++d) st_off(X[d], o, x2[j][d]);
-#pragma unroll
-                        for (int m = 0; m < 3; ++m) st_off(V[m], o, u[j][m]);
-                        if (p.ids) st_off(p.ids + so, k * 4u, origin);
-                    } else if (valid[j]) {
+                        for (int d = 0; d < 3; ++d) pend[j].x2[d] = x2[j][d];
+                    } else {
                         int64_t slot = nleave + (lane_idx - pre[j]);
-                        if (slot >= p.ob_cap) {
+                        if (valid[j] && slot >= p.ob_cap) {
                             errs |= ERR_CAPACITY;     // state is invalid from here on
                             slot = p.ob_cap - 1;
                         }
-                        const uint32_t o = (uint32_t)slot * (uint32_t)sizeof(R);
+                        pend[j].off = (uint32_t)slot * (uint32_t)sizeof(R);
 #pragma unroll
-                        for (int d = 0; d < D; ++d) st_off(OX[d], o, x2[j][d] - R(delta[j][d] * T[d]));
-#pragma unroll
-                        for (int m = 0; m < 3; ++m) st_off(OU[m], o, u[j][m]);
-                        st_off(OD, (uint32_t)slot * 4u, code[j]);
-                        if (p.ids) st_off(p.ob_ids + ob, (uint32_t)slot * 4u, origin);
+                        for (int d = 0; d < 3; ++d) pend[j].x2[d] = x2[j][d] - R(delta[j][d] * T[d]);
                     }
                 }
                 const int nvalid = min(G, cnt - c0);
@@ -393,6 +447,7 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int w, unsig
             }
         }
         if constexpr (FUSED) {
+            flush_pending();                           // the last group's stores
             if (threadIdx.x == 0) {
                 p.seg_cnt[ts] = keep;
                 p.ob_cnt[ts] = nleave;

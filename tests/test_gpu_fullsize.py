@@ -2,7 +2,8 @@
 times (fused push with push_half_b1 in LDS, tile edge 16).
 
 * Decaying turbulence, 1024^2 cells, 16 particles per cell per species
-  (33.5 M particles), one step from the GPU's own state, FP32 and FP64,
+  (33.5 M particles), one step from the GPU's own state after 5 steps (E
+  no longer zero), FP32 and FP64,
   against the oracle on the whole lattice: E, B and J on every cell, u and x
   of every particle (matched across the migration through origin ids).
   Where floating point decides an integer, both sides take the decision in
@@ -51,7 +52,9 @@ def test_turbulence_full_size_whole_lattice(prec):
     plasma = synth.turbulence(n=n, ppc=16)
     print(f"[gpu] turbulence {n}^2, {plasma.nparticles} particles, {prec}, T=16, whole lattice", flush=True)
     sim = PicSim(plasma, tile=T[:2], precision=prec, capacity_factor=3.0, options=L.PIC_OPT_TRACK)
+    sim.step(5, fused=True, half_b_in_push=True)
     E0, B0, _ = sim.fields_host(0)
+    assert np.abs(E0).max() > 0
     pre = []
     for s in range(2):
         tid, xl, u = sim.particles_host(0, s)

@@ -94,7 +94,9 @@ def test_walls_fused_step_matches_oracle(D, n, T, ppc, prec):
         assert np.array_equal(pre[s][k], origin)
         ptol = 1e-12 if prec == "fp64" else 4e-6 * max(T)
         assert np.abs(gx - st.x[s][:, k]).max() < ptol
-        assert rel(u.astype(np.float64), st.u[s][:, k]) < tol * 10
+        print(f"[gpu] walls D={D} {prec} species {s}: rel L2 u {rel(u.astype(np.float64), st.u[s][:, k]):.3e}, "
+              f"max |dx| {np.abs(gx - st.x[s][:, k]).max():.3e}", flush=True)
+        assert rel(u.astype(np.float64), st.u[s][:, k]) < tol
         assert gx[0].min() >= 0.0 and gx[0].max() < n[0]
     assert reflected > 0, "no particle reached a wall"
     sim.close()
