@@ -31,12 +31,12 @@ METRIC = "particle-steps/sec (push+deposit+FDTD) FP32 vs FP64 at 1 GPU; % HBM ro
 
 # HBM bytes per launch of the fused push, measured with rocprofv3 --pmc
 # FETCH_SIZE and WRITE_SIZE on the turbulence workload and scaled by a plain
-# 1 GiB device copy (FETCH x 2.000, WRITE x 1.000), averaged over the 505
-# launches of a whole run.  Keyed by the hash of the
+# 1 GiB device copy (FETCH x 2.000, WRITE x 1.000), averaged over the first 60
+# launches of a run.  Keyed by the hash of the
 # kernel sources they were measured on, precision, tile edge, cells per side
 # and particles per cell: any other kernel reports no traffic.
 MEASURED_PUSH_TRAFFIC = {
-    ("4308cd53ae39b913", "fp32", 16, 1024, 16): 1674695680,
+    ("e183b92409cd7f7f", "fp32", 16, 1024, 16): 1668508292,
 }
 
 
@@ -73,7 +73,10 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many fused steps (for rocprofv3), no JSON")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"],
-                    help="precision of the --profile-steps run")
+                    help="precision of the --profile-steps and --step-trace runs")
+    ap.add_argument("--step-trace", type=int, default=0,
+                    help="only run this many fused steps and print every step's kernel times "
+                         "(HIP events on the library's stream) as one JSON line, no headline")
     ap.add_argument("--capacity", type=float, default=8.0,
                     help="tile segment capacity over the mean count: the turbulent plasma compresses "
                          "16x16-cell tiles to about 4.6 times the mean count within 100 steps")
@@ -202,6 +205,45 @@ def cpu_model() -> str:
     except OSError:
         pass
     return "unknown"
+
+
+def step_trace(plasma, args, tile, block):
+    """Every step's kernel times (us) over args.step_trace fused steps of
+    the workload: the push, the two half B updates, the fold with the E
+    update, the migration, from HIP events on the library's stream."""
+    import torch
+    from paper_1906_06306_amd import _lib as L
+    from paper_1906_06306_amd.sim import PicSim
+    sim = PicSim(plasma, tile=(tile, tile), precision=args.precision, block=block, capacity_factor=args.capacity)
+    lib, ctx = L.lib(), sim.ctx
+    stream = torch.cuda.current_stream()
+    flags = L.PIC_FUSED | L.PIC_PUSH_HALF_B
+    rows = []
+    for k in range(args.step_trace):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        ev[0].record(stream)
+        L.check(lib.pic_push_interp(ctx, L.PIC_ALL_SPECIES, flags))
+        ev[1].record(stream)
+        L.check(lib.pic_fdtd_step(ctx, L.PIC_TWO_HALF_B))
+        ev[2].record(stream)
+        L.check(lib.pic_deposit_current(ctx, L.PIC_ALL_SPECIES, flags | L.PIC_DEPOSIT_CURL_E))
+        ev[3].record(stream)
+        L.check(lib.pic_sort_migrate(ctx, 0, None, None, 0))
+        ev[4].record(stream)
+        rows.append(ev)
+        if k % 100 == 0:
+            log(f"step trace: step {k} enqueued")
+    torch.cuda.synchronize()
+    t = np.array([[r[i].elapsed_time(r[i + 1]) * 1e3 for i in range(4)] for r in rows])
+    status = sim.error()
+    sim.close()
+    out = {"workload": "turbulence", "precision": args.precision, "tile": tile, "block": block,
+           "status": status, "columns": ["push", "two_half_b", "fold_e", "migrate"],
+           "us_per_step": [[round(v, 1) for v in row] for row in t.tolist()]}
+    for a, b in ((5, 25), (0, len(t)), (100, len(t))):
+        if b > a:
+            out[f"mean_steps_{a}_{b}"] = {"push": float(t[a:b, 0].mean()), "step": float(t[a:b].sum(1).mean())}
+    print(json.dumps(out), flush=True)
 
 
 def cpu_oracle_rate(plasma, steps, threads=1):
@@ -699,6 +741,10 @@ def main():
         code = run_gpu(plasma, args, args.precision, args.profile_steps, 0, tile, args.block or 256, profile_only=True)
         log(f"profile run done, device status {code}")
         return
+    if args.step_trace:
+        tile = 16 if args.tile == "auto" else int(args.tile)
+        step_trace(plasma, args, tile, args.block or 256)
+        return
     tile32, blk32, tune32 = pick_tile(plasma, args, "fp32")
     log(f"fp32 run, tile {tile32}, block {blk32}")
     r32 = run_gpu(plasma, args, "fp32", args.steps, args.warmup, tile32, blk32)
@@ -761,7 +807,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": MEASURED_PUSH_TRAFFIC.get((kernel_source_hash(), "fp32", tile32, args.n, args.ppc)),
                      "traffic_source": "stored: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE of this kernel on this "
-                                       "workload, scaled by a plain copy, averaged over a whole run, for the kernel "
+                                       "workload, scaled by a plain copy, averaged over 60 launches, for the kernel "
                                        "sources with the hash kernel_sources (null for other sources)",
                      "kernel": "k_push<float,2,fused>", "push_ms": r32["push_ms"],
                      "algorithmic_bytes_per_launch": pb, "kernel_sources": kernel_source_hash(),
