@@ -502,12 +502,17 @@ struct Impl {
         if (x->pusher == PIC_PUSHER_HC)
             return x->walls ? push_launch<FUSED, HALFB, A, 0, FUSED, pic::PUSHER_HC>(x)
                             : push_launch<FUSED, HALFB, A, 0, false, pic::PUSHER_HC>(x);
+        bool cubic = true;
+        for (int d = 1; d < D; ++d) cubic = cubic && x->T[d] == x->T[0];
         if constexpr (FUSED) {
-            if (x->walls) return push_launch<FUSED, HALFB, A, 0, true, pic::PUSHER_BORIS>(x);
+            if (x->walls) {
+                // the 3D shock's tiles: edge 8 as a constant
+                if constexpr (D == 3 && (std::is_same<A, double>::value || std::is_same<A, long long>::value))
+                    if (cubic && x->T[0] == 8) return push_launch<FUSED, HALFB, A, 8, true, pic::PUSHER_BORIS>(x);
+                return push_launch<FUSED, HALFB, A, 0, true, pic::PUSHER_BORIS>(x);
+            }
         }
         if constexpr (FUSED && (std::is_same<A, double>::value || std::is_same<A, long long>::value)) {
-            bool cubic = true;
-            for (int d = 1; d < D; ++d) cubic = cubic && x->T[d] == x->T[0];
             if (cubic && x->T[0] == 8) return push_launch<FUSED, HALFB, A, 8, false, pic::PUSHER_BORIS>(x);
             if (cubic && x->T[0] == 16) return push_launch<FUSED, HALFB, A, 16, false, pic::PUSHER_BORIS>(x);
             if constexpr (D < 3)
