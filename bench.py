@@ -77,6 +77,12 @@ def parse():
     ap.add_argument("--step-trace", type=int, default=0,
                     help="only run this many fused steps and print every step's kernel times "
                          "(HIP events on the library's stream) as one JSON line, no headline")
+    ap.add_argument("--clock-probe", action="store_true",
+                    help="with --step-trace: after every step also time a fixed-cycle spin kernel "
+                         "(20,000 shader-clock cycles: its duration follows the core clock) and a "
+                         "256 MiB device copy (HBM bandwidth)")
+    ap.add_argument("--pause-at", type=int, default=0,
+                    help="with --step-trace: leave the GPU idle for 3 s before this step")
     ap.add_argument("--capacity", type=float, default=8.0,
                     help="tile segment capacity over the mean count: the turbulent plasma compresses "
                          "16x16-cell tiles to about 4.6 times the mean count within 100 steps")
@@ -218,9 +224,17 @@ def step_trace(plasma, args, tile, block):
     lib, ctx = L.lib(), sim.ctx
     stream = torch.cuda.current_stream()
     flags = L.PIC_FUSED | L.PIC_PUSH_HALF_B
+    probe = args.clock_probe
+    if probe:
+        src = torch.empty(32 << 20, dtype=torch.float64, device=sim.device)   # 256 MiB
+        dst = torch.empty_like(src)
     rows = []
+    torch.cuda.synchronize()
     for k in range(args.step_trace):
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        if args.pause_at and k == args.pause_at:
+            torch.cuda.synchronize()
+            time.sleep(3.0)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(7 if probe else 5)]
         ev[0].record(stream)
         L.check(lib.pic_push_interp(ctx, L.PIC_ALL_SPECIES, flags))
         ev[1].record(stream)
@@ -230,6 +244,11 @@ def step_trace(plasma, args, tile, block):
         ev[3].record(stream)
         L.check(lib.pic_sort_migrate(ctx, 0, None, None, 0))
         ev[4].record(stream)
+        if probe:
+            torch.cuda._sleep(20000)
+            ev[5].record(stream)
+            dst.copy_(src)
+            ev[6].record(stream)
         rows.append(ev)
         if k % 100 == 0:
             log(f"step trace: step {k} enqueued")
@@ -240,9 +259,21 @@ def step_trace(plasma, args, tile, block):
     out = {"workload": "turbulence", "precision": args.precision, "tile": tile, "block": block,
            "status": status, "columns": ["push", "two_half_b", "fold_e", "migrate"],
            "us_per_step": [[round(v, 1) for v in row] for row in t.tolist()]}
-    for a, b in ((5, 25), (0, len(t)), (100, len(t))):
-        if b > a:
+    if args.pause_at:
+        out["idle_3s_before_step"] = args.pause_at
+    if probe:
+        spin = [r[4].elapsed_time(r[5]) * 1e3 for r in rows]
+        cp = [2 * src.numel() * 8 / (r[5].elapsed_time(r[6]) * 1e-3) / 1e9 for r in rows]
+        out["spin_20k_cycles_us"] = [round(v, 1) for v in spin]
+        out["copy_256MiB_GBs"] = [round(v) for v in cp]
+    wins = [(5, 25), (30, 60), (0, len(t)), (100, len(t))]
+    if args.pause_at:
+        wins += [(args.pause_at - 30, args.pause_at), (args.pause_at + 5, args.pause_at + 25)]
+    for a, b in wins:
+        if 0 <= a < b <= len(t):
             out[f"mean_steps_{a}_{b}"] = {"push": float(t[a:b, 0].mean()), "step": float(t[a:b].sum(1).mean())}
+            if probe:
+                out[f"mean_steps_{a}_{b}"]["spin_20k_cycles_us"] = float(np.mean(spin[a:b]))
     print(json.dumps(out), flush=True)
 
 

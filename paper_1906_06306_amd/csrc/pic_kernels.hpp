@@ -541,25 +541,44 @@ __global__ void __launch_bounds__(1024) k_deposit(Params<R> p)
     for (int k = threadIdx.x; k < 3 * cb.n; k += blockDim.x) blk[k] = (R)sJ[k];
 }
 
-// E += h curl- B at one cell with the second-order backward differences of
-// App. B (periodic inside the box), then E -= j when SUB_J; the tangential
-// E vanishes on a wall plane.  Reads B and only this cell's E.
-template <typename R, int D, bool SUB_J>
-__device__ __forceinline__ void curl_b_update_e(const Params<R> &p, const TileDesc &td, int gx, int gy, int gz,
-                                                int64_t g, R h, const R j[3])
+// Inputs of the E update at one cell: E there, B there (b) and B at the
+// cell below along each axis a (bm[a]; the cell itself along axes at or
+// beyond D), periodic inside the box.
+template <typename R, int D>
+__device__ __forceinline__ void load_e_update(const Params<R> &p, const TileDesc &td, int gx, int gy, int gz,
+                                              int64_t g, R e[3], R b[3], R bm[3][3])
 {
     const int64_t N = p.cells_total;
     const int n0 = td.n[0], n1 = td.n[1], n2 = td.n[2];
     auto at = [&](int x, int y, int z) -> int64_t { return td.cell0 + x + (int64_t)n0 * (y + (int64_t)n1 * z); };
-    const R *Bx = p.B, *By = p.B + N, *Bz = p.B + 2 * N;
-    const int64_t im = at(gx == 0 ? n0 - 1 : gx - 1, gy, gz);
-    const int64_t jm = D > 1 ? at(gx, gy == 0 ? n1 - 1 : gy - 1, gz) : g;
-    const int64_t km = D > 2 ? at(gx, gy, gz == 0 ? n2 - 1 : gz - 1) : g;
-    const R bx = Bx[g], by = By[g], bz = Bz[g];
-    const R cx = (bz - Bz[jm]) - (by - By[km]);
-    const R cy = (bx - Bx[km]) - (bz - Bz[im]);
-    const R cz = (by - By[im]) - (bx - Bx[jm]);
-    R ex = p.E[g] + h * cx, ey = p.E[N + g] + h * cy, ez = p.E[2 * N + g] + h * cz;
+    const int64_t m[3] = {at(gx == 0 ? n0 - 1 : gx - 1, gy, gz), D > 1 ? at(gx, gy == 0 ? n1 - 1 : gy - 1, gz) : g,
+                          D > 2 ? at(gx, gy, gz == 0 ? n2 - 1 : gz - 1) : g};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        e[c] = p.E[c * N + g];
+        b[c] = p.B[c * N + g];
+    }
+    // the six neighbour values the curl uses
+    bm[0][1] = p.B[N + m[0]];
+    bm[0][2] = p.B[2 * N + m[0]];
+    bm[1][0] = p.B[m[1]];
+    bm[1][2] = p.B[2 * N + m[1]];
+    bm[2][0] = p.B[m[2]];
+    bm[2][1] = p.B[N + m[2]];
+}
+
+// E += h curl- B at one cell with the second-order backward differences of
+// App. B, then E -= j when SUB_J; the tangential E vanishes on a wall plane.
+// Takes the values load_e_update read.
+template <typename R, int D, bool SUB_J>
+__device__ __forceinline__ void update_e_cell(const Params<R> &p, const TileDesc &td, int gx, int64_t g, R h,
+                                              const R j[3], const R e[3], const R b[3], const R bm[3][3])
+{
+    const int64_t N = p.cells_total;
+    const R cx = (b[2] - bm[1][2]) - (b[1] - bm[2][1]);
+    const R cy = (b[0] - bm[2][0]) - (b[2] - bm[0][2]);
+    const R cz = (b[1] - bm[0][1]) - (b[0] - bm[1][0]);
+    R ex = e[0] + h * cx, ey = e[1] + h * cy, ez = e[2] + h * cz;
     if constexpr (SUB_J) {
         ex -= j[0];
         ey -= j[1];
@@ -569,6 +588,48 @@ __device__ __forceinline__ void curl_b_update_e(const Params<R> &p, const TileDe
     p.E[g] = ex;
     p.E[N + g] = ey;
     p.E[2 * N + g] = ez;
+}
+
+// E += h curl- B (- j) at one cell.
+template <typename R, int D, bool SUB_J>
+__device__ __forceinline__ void curl_b_update_e(const Params<R> &p, const TileDesc &td, int gx, int gy, int gz,
+                                                int64_t g, R h, const R j[3])
+{
+    R e[3], b[3], bm[3][3];
+    load_e_update<R, D>(p, td, gx, gy, gz, g, e, b, bm);
+    update_e_cell<R, D, SUB_J>(p, td, gx, g, h, j, e, b, bm);
+}
+
+// B -= h curl+ E at one cell (global indices gx, gy, gz, storage index g),
+// twice when TWICE (both half updates of Table 1 with the same E): the
+// forward differences of App. B, periodic inside the box.  Returns the new B.
+template <typename R, int D, bool TWICE>
+__device__ __forceinline__ void update_b_cell(const Params<R> &p, const TileDesc &td, int gx, int gy, int gz,
+                                              int64_t g, R h, R b[3])
+{
+    const int64_t N = p.cells_total;
+    const int n0 = td.n[0], n1 = td.n[1], n2 = td.n[2];
+    auto at = [&](int x, int y, int z) -> int64_t { return td.cell0 + x + (int64_t)n0 * (y + (int64_t)n1 * z); };
+    const R *Ex = p.E, *Ey = p.E + N, *Ez = p.E + 2 * N;
+    const int64_t ip = D > 0 ? at(gx + 1 == n0 ? 0 : gx + 1, gy, gz) : g;
+    const int64_t jp = D > 1 ? at(gx, gy + 1 == n1 ? 0 : gy + 1, gz) : g;
+    const int64_t kp = D > 2 ? at(gx, gy, gz + 1 == n2 ? 0 : gz + 1) : g;
+    const R ex = Ex[g], ey = Ey[g], ez = Ez[g];
+    const R cx = (Ez[jp] - ez) - (Ey[kp] - ey);
+    const R cy = (Ex[kp] - ex) - (Ez[ip] - ez);
+    const R cz = (Ey[ip] - ey) - (Ex[jp] - ex);
+    R bx = p.B[g], by = p.B[N + g], bz = p.B[2 * N + g];
+    bx -= h * cx;
+    by -= h * cy;
+    bz -= h * cz;
+    if constexpr (TWICE) {
+        bx -= h * cx;
+        by -= h * cy;
+        bz -= h * cz;
+    }
+    b[0] = bx;
+    b[1] = by;
+    b[2] = bz;
 }
 
 // cur_exchange: J on the lattice = sum of the current blocks (one per
@@ -594,6 +655,15 @@ __global__ void __launch_bounds__(256) k_fold(Params<R> p, R h)
     for (int d = 0; d < D; ++d) small = small || p.T[d] < 4;
     for (int k = threadIdx.x; k < ncell; k += blockDim.x) {
         const int l[3] = {k % T0, (k / T0) % T1, k / (T0 * T1)};
+        const int gx = td.tc[0] * T0 + l[0];
+        const int gy = D > 1 ? td.tc[1] * T1 + l[1] : 0;
+        const int gz = D > 2 ? td.tc[2] * T2 + l[2] : 0;
+        const int64_t g = td.cell0 + gx + (int64_t)td.n[0] * (gy + (int64_t)td.n[1] * gz);
+        // the E update's inputs first: loaded before the J stores below (which
+        // the compiler may not move them across), all of the cell's loads are
+        // in flight together
+        R ee[3], eb[3], ebm[3][3];
+        if constexpr (CURL_E) load_e_update<R, D>(p, td, gx, gy, gz, g, ee, eb, ebm);
         R acc[3] = {0, 0, 0};
         if (!small) {
             // per dimension: offsets o0 < o1 and whether o1 covers the cell
@@ -637,7 +707,11 @@ __global__ void __launch_bounds__(256) k_fold(Params<R> p, R h)
                 for (int cmb = 0; cmb < NCOMB; ++cmb) {
                     const R *blk = p.jblk + (base[cmb] + sp) * 3 * cb.n + idx[cmb];
 #pragma unroll
-                    for (int m = 0; m < 3; ++m) v[cmb][m] = blk[m * cb.n];
+                    for (int m = 0; m < 3; ++m) v[cmb][m] = R(0);
+                    if (cmb == 0 || ok[cmb]) {
+#pragma unroll
+                        for (int m = 0; m < 3; ++m) v[cmb][m] = blk[m * cb.n];
+                    }
                 }
 #pragma unroll
                 for (int cmb = 0; cmb < NCOMB; ++cmb) {
@@ -671,14 +745,10 @@ __global__ void __launch_bounds__(256) k_fold(Params<R> p, R h)
                         }
             }
         }
-        const int gx = td.tc[0] * T0 + l[0];
-        const int gy = D > 1 ? td.tc[1] * T1 + l[1] : 0;
-        const int gz = D > 2 ? td.tc[2] * T2 + l[2] : 0;
-        const int64_t g = td.cell0 + gx + (int64_t)td.n[0] * (gy + (int64_t)td.n[1] * gz);
         p.J[g] = acc[0];
         p.J[p.cells_total + g] = acc[1];
         p.J[2 * p.cells_total + g] = acc[2];
-        if constexpr (CURL_E) curl_b_update_e<R, D, true>(p, td, gx, gy, gz, g, h, acc);
+        if constexpr (CURL_E) update_e_cell<R, D, true>(p, td, gx, g, h, acc, ee, eb, ebm);
     }
 }
 
@@ -748,26 +818,11 @@ __global__ void __launch_bounds__(256) k_field(Params<R> p, R h)
             p.E[N + g] = ey;
             p.E[2 * N + g] = ez;
         } else if constexpr (PHASE == 0 || PHASE == 4) {
-            const R *Ex = p.E, *Ey = p.E + N, *Ez = p.E + 2 * N;
-            const int64_t ip = D > 0 ? at(gx + 1 == n0 ? 0 : gx + 1, gy, gz) : g;
-            const int64_t jp = D > 1 ? at(gx, gy + 1 == n1 ? 0 : gy + 1, gz) : g;
-            const int64_t kp = D > 2 ? at(gx, gy, gz + 1 == n2 ? 0 : gz + 1) : g;
-            const R ex = Ex[g], ey = Ey[g], ez = Ez[g];
-            const R cx = (Ez[jp] - ez) - (Ey[kp] - ey);
-            const R cy = (Ex[kp] - ex) - (Ez[ip] - ez);
-            const R cz = (Ey[ip] - ey) - (Ex[jp] - ex);
-            R bx = p.B[g], by = p.B[N + g], bz = p.B[2 * N + g];
-            bx -= h * cx;
-            by -= h * cy;
-            bz -= h * cz;
-            if constexpr (PHASE == 4) {
-                bx -= h * cx;
-                by -= h * cy;
-                bz -= h * cz;
-            }
-            p.B[g] = bx;
-            p.B[N + g] = by;
-            p.B[2 * N + g] = bz;
+            R b[3];
+            update_b_cell<R, D, PHASE == 4>(p, td, gx, gy, gz, g, h, b);
+            p.B[g] = b[0];
+            p.B[N + g] = b[1];
+            p.B[2 * N + g] = b[2];
         } else if constexpr (PHASE == 2) {
             const bool wall = (td.walls & 1) && gx == 0;
             p.E[g] -= p.J[g];
