@@ -602,7 +602,7 @@ __device__ __forceinline__ void curl_b_update_e(const Params<R> &p, const TileDe
 
 // B -= h curl+ E at one cell (global indices gx, gy, gz, storage index g),
 // twice when TWICE (both half updates of Table 1 with the same E): the
-// forward differences of App. B, periodic inside the box.  Returns the new B.
+// forward differences of App. B, periodic inside the box.  The new B goes to b.
 template <typename R, int D, bool TWICE>
 __device__ __forceinline__ void update_b_cell(const Params<R> &p, const TileDesc &td, int gx, int gy, int gz,
                                               int64_t g, R h, R b[3])
@@ -637,11 +637,12 @@ __device__ __forceinline__ void update_b_cell(const Params<R> &p, const TileDesc
 // a fixed order (species, then neighbour offsets ascending, z major).  A
 // block covers local cells -1..T+1, so along each dimension a cell is
 // covered by its own tile and, for l < 2, the tile below or, for l = T-1,
-// the tile above (edges T >= 4); the up to 2^D loads of a species are
-// issued together, without branches.  Edges of 2 take the general loop.
-// With CURL_E the same pass also applies E += h curl- B - J to the cell
-// (push_e and add_cur after the second half update of B), from the folded
-// values still in registers: J is written once and not read back.
+// the tile above (edges T >= 4); a cell loads the blocks that cover it
+// (interior cells their own tile's alone), and an uncovered combination
+// adds 0.  Edges of 2 take the general loop.  With CURL_E the same pass
+// also applies E += h curl- B - J to the cell (push_e and add_cur after the
+// second half update of B), from the folded values still in registers: J
+// is written once and not read back.
 template <typename R, int D, bool CURL_E>
 __global__ void __launch_bounds__(256) k_fold(Params<R> p, R h)
 {
