@@ -41,6 +41,15 @@ MEASURED_PUSH_TRAFFIC = {
     ("0681571432fda81a", "fp64", 16, 1024, 16): 3196000366,
 }
 
+# wave64 VALU instructions per 64 particles of the same push, from rocprofv3
+# --pmc SQ_INSTS_VALU over the first 40 launches of a run (same key), and the
+# chip's VALU issue peak: 256 CUs x 4 SIMDs, one wave64 instruction per 4
+# clocks per SIMD (16 lanes; FP32 not packed) at 2.4 GHz
+MEASURED_PUSH_VALU_PER_64 = {
+    ("0681571432fda81a", "fp32", 16, 1024, 16): 392.0,
+}
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
+
 
 def strip_comments(src: str) -> str:
     """C/C++ source without comments and with whitespace runs collapsed, so
@@ -220,6 +229,19 @@ def run_gpu(plasma, args, precision, steps, warmup, tile, block=256, profile_onl
     del sim
     torch.cuda.empty_cache()
     return dict(seconds=dt, push_ms=push_ms, diag=diag, later=later)
+
+
+def valu_roofline(key_hash, prec, tile, args, n_p, push_ms):
+    """The push against its VALU issue rate: the measured instructions per
+    64 particles for this code, issued in push_ms, over VALU_ISSUE_PEAK
+    (null for code without a measurement)."""
+    per64 = MEASURED_PUSH_VALU_PER_64.get((key_hash, prec, tile, args.n, args.ppc))
+    if per64 is None:
+        return None
+    achieved = per64 * (n_p / 64.0) / (push_ms * 1e-3)
+    return {"bound": "valu_issue", "instr_per_64_particles": per64, "achieved": achieved,
+            "peak": VALU_ISSUE_PEAK, "unit": "wave64 instr/s", "frac": achieved / VALU_ISSUE_PEAK,
+            "source": "stored: rocprofv3 --pmc SQ_INSTS_VALU of this kernel code on this workload"}
 
 
 def host_threads() -> int:
@@ -874,6 +896,7 @@ def main():
                      "algorithmic_bytes_per_launch": pb, "kernel_sources": kernel_source_hash(),
                      "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "step_roofline_frac": algorithmic_bytes(D, 4, n_p, n_c) * value / n_p / 1e9 / HBM_PEAK_GBS,
+        "valu_roofline": valu_roofline(kernel_source_hash(), "fp32", tile32, args, n_p, r32["push_ms"]),
         "same_run_steps_40_60": r32["later"],
         "diagnostics_fp32": {k: r32["diag"][k] for k in ("gauss_max", "continuity_max", "divb_max", "field_energy",
                                                          "kinetic_energy", "particles", "near_face",
