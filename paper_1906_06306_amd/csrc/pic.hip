@@ -421,7 +421,7 @@ struct Impl {
             cbn *= x->T[d] + 3;
         }
         return (3 * cbn + 3 * fbn) * sizeof(R) + (fused ? 3 * cbn * acc_bytes : 0) +
-               (2 * PUSH_UNROLL * pic::MAX_WAVES + 4) * sizeof(int);
+               (2 * PUSH_UNROLL * pic::MAX_WAVES + 4 + (fused ? pic::bucket_lds_ints<D>() : 0)) * sizeof(int);
     }
 
     template <int ORDER>
@@ -572,7 +572,10 @@ struct Impl {
             // one small work-group per (tile, species) segment: both kernels
             // are chains of dependent loads, so many resident groups pay
             const dim3 gs((unsigned)(x->L.pub.tiles_total * x->ns));
-            hipLaunchKernelGGL((pic::k_migrate_bucket<R, D>), gs, dim3(128), 0, x->stream, p);
+            // the fused push buckets its own outbox; the unfused path (and a
+            // call that wants the migration counts) runs the bucket pass here
+            if (need_out || mig_counts)
+                hipLaunchKernelGGL((pic::k_migrate_bucket<R, D>), gs, dim3(128), 0, x->stream, p);
             hipLaunchKernelGGL((pic::k_migrate_in<R, D>), gs, dim3(128), 0, x->stream, p);
             HIP_OK(hipGetLastError());
         }

@@ -90,6 +90,77 @@ __device__ __forceinline__ int wg_scan_flags(const bool f[U], int *sTot, int par
     return run;
 }
 
+// Stable counting sort of one segment's n outbox entries by direction code:
+// the bucket starts ob_boff[ncodes + 1] and the outbox slots in bucket order
+// ob_idx, so that each neighbour reads exactly the leavers addressed to it.
+// The rank of an entry among equal codes of its wave comes from ballots on
+// the code bits; waves are ordered through per-wave counts in LDS.  With
+// mig_counts, also the segment's migration counts by direction code.  Called
+// by the whole work-group (barriers inside).
+template <typename R, int D>
+__device__ __forceinline__ void bucket_outbox(const Params<R> &p, const int ts, const int n, int *sCnt, int *sBase)
+{
+    // sCnt: MAX_WAVES * ncodes ints, sBase: ncodes + 1 ints of LDS
+    constexpr int NC = ncodes<D>();
+    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int32_t *dir = p.ob_dir + (int64_t)ts * p.ob_dir_stride;
+    int32_t *boff = p.ob_boff + (int64_t)ts * (NC + 1);
+    int32_t *idx = p.ob_idx + (int64_t)ts * p.ob_cap;
+    // histogram and bucket starts
+    for (int k = threadIdx.x; k <= NC; k += blockDim.x) sBase[k] = 0;
+    __syncthreads();
+    for (int k = threadIdx.x; k < n; k += blockDim.x) atomicAdd(&sBase[dir[k] + 1], 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int c = 0; c < NC; ++c) sBase[c + 1] += sBase[c];
+        for (int c = 0; c <= NC; ++c) boff[c] = sBase[c];
+        if (p.mig_counts) {
+            // particles of the segment by the tile they went to: the
+            // outbox buckets, and the stayers at the centre code (the
+            // segment count before the arrivals are appended)
+            int32_t *mc = p.mig_counts + (int64_t)ts * NC;
+            for (int c = 0; c < NC; ++c) mc[c] = c == centre_code<D>() ? p.seg_cnt[ts] : sBase[c + 1] - sBase[c];
+        }
+    }
+    __syncthreads();
+    // stable scatter, one work-group-wide chunk at a time
+    for (int c0 = 0; c0 < n; c0 += blockDim.x) {
+        for (int k = threadIdx.x; k < nw * NC; k += blockDim.x) sCnt[k] = 0;
+        __syncthreads();
+        const int k = c0 + (int)threadIdx.x;
+        const bool valid = k < n;
+        const int code = valid ? dir[k] : 0;
+        unsigned long long m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 5; ++b) {
+            const unsigned long long bb = __ballot((code >> b) & 1);
+            m &= ((code >> b) & 1) ? bb : ~bb;
+        }
+        const int rank = lanes_below(m);
+        if (valid && rank == 0) sCnt[wave * NC + code] = __popcll(m);
+        __syncthreads();
+        if (valid) {
+            int off = sBase[code] + rank;
+            for (int w = 0; w < wave; ++w) off += sCnt[w * NC + code];
+            idx[off] = k;
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < NC) {
+            int add = 0;
+            for (int w = 0; w < nw; ++w) add += sCnt[w * NC + threadIdx.x];
+            sBase[threadIdx.x] += add;
+        }
+        __syncthreads();
+    }
+}
+
+// LDS ints of bucket_outbox's scratch.
+template <int D>
+__host__ __device__ constexpr int bucket_lds_ints()
+{
+    return MAX_WAVES * ncodes<D>() + ncodes<D>() + 1;
+}
+
 template <typename R, int D>
 __device__ __forceinline__ bool inside_tile(const R x[3], const int32_t T[3])
 {
@@ -200,6 +271,7 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int w, unsig
     R *sB = sE + 3 * cb.n;
     int *sTot = reinterpret_cast<int *>(sB + 3 * fb.n);
     int *sNF = sTot + 2 * U * MAX_WAVES;   // particles left near a cell face
+    int *sBkt = sNF + 4;                    // bucket_outbox scratch (fused push)
     if (threadIdx.x == 0) *sNF = 0;
     stage_block<R, D>(p.E, p.cells_total, td, T, sE, cb);
     stage_block<R, D>(p.B, p.cells_total, td, T, sB, fb);
@@ -452,6 +524,11 @@ __device__ __forceinline__ void push_tile(const Params<R> &p, const int w, unsig
                 p.seg_cnt[ts] = keep;
                 p.ob_cnt[ts] = nleave;
             }
+            // bucket the outbox by direction code for the migration; the
+            // barrier makes every wave's outbox stores visible to the group
+            __syncthreads();
+            bucket_outbox<R, D>(p, ts, (int)min((int64_t)nleave, p.ob_cap), sBkt,
+                                sBkt + MAX_WAVES * ncodes<D>());
         }
     }
     latch_wave(p.err, errs);
@@ -915,77 +992,20 @@ __global__ void __launch_bounds__(1024) k_migrate_out(Params<R> p)
     }
 }
 
-// Bucket every tile's outbox by direction code (stable counting sort): for
-// each (tile, species) the bucket starts ob_boff[ncodes + 1] and the outbox
-// slots in bucket order ob_idx[ob_cap], so that each neighbour reads exactly
-// the leavers addressed to it.  With mig_counts, also the segment's
-// migration counts by direction code.  The rank of an entry among equal codes of
-// its wave comes from ballots on the code bits; waves are ordered through
-// per-wave counts in LDS.
+// Bucket every segment's outbox by direction code (bucket_outbox), one
+// work-group per segment: after an unfused push's k_migrate_out, and for the
+// migration counts (the fused push buckets its own outbox at its end).
 template <typename R, int D>
 __global__ void __launch_bounds__(1024) k_migrate_bucket(Params<R> p)
 {
-    constexpr int NC = ncodes<D>();
-    __shared__ int sCnt[MAX_WAVES * NC];
-    __shared__ int sBase[NC + 1];
+    __shared__ int sScratch[bucket_lds_ints<D>()];
     // one work-group per (tile, species) segment
     const int ts = xcd_tile(blockIdx.x, gridDim.x);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    {
-        // species_mask: the species pushed in this step; the outboxes of the
-        // others hold nothing of this step
-        const int s = ts % p.nspecies;
-        const int n = ((p.species_mask >> s) & 1u) ? (int)min((int64_t)p.ob_cnt[ts], p.ob_cap) : 0;
-        const int32_t *dir = p.ob_dir + (int64_t)ts * p.ob_dir_stride;
-        int32_t *boff = p.ob_boff + (int64_t)ts * (NC + 1);
-        int32_t *idx = p.ob_idx + (int64_t)ts * p.ob_cap;
-        // histogram and bucket starts
-        for (int k = threadIdx.x; k <= NC; k += blockDim.x) sBase[k] = 0;
-        __syncthreads();
-        for (int k = threadIdx.x; k < n; k += blockDim.x) atomicAdd(&sBase[dir[k] + 1], 1);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            for (int c = 0; c < NC; ++c) sBase[c + 1] += sBase[c];
-            for (int c = 0; c <= NC; ++c) boff[c] = sBase[c];
-            if (p.mig_counts) {
-                // particles of the segment by the tile they went to: the
-                // outbox buckets, and the stayers at the centre code (the
-                // segment count before the arrivals are appended)
-                int32_t *mc = p.mig_counts + (int64_t)ts * NC;
-                for (int c = 0; c < NC; ++c) mc[c] = c == centre_code<D>() ? p.seg_cnt[ts] : sBase[c + 1] - sBase[c];
-            }
-        }
-        __syncthreads();
-        // stable scatter, one work-group-wide chunk at a time
-        for (int c0 = 0; c0 < n; c0 += blockDim.x) {
-            for (int k = threadIdx.x; k < nw * NC; k += blockDim.x) sCnt[k] = 0;
-            __syncthreads();
-            const int k = c0 + (int)threadIdx.x;
-            const bool valid = k < n;
-            const int code = valid ? dir[k] : 0;
-            unsigned long long m = __ballot(valid);
-#pragma unroll
-            for (int b = 0; b < 5; ++b) {
-                const unsigned long long bb = __ballot((code >> b) & 1);
-                m &= ((code >> b) & 1) ? bb : ~bb;
-            }
-            const int rank = lanes_below(m);
-            if (valid && rank == 0) sCnt[wave * NC + code] = __popcll(m);
-            __syncthreads();
-            if (valid) {
-                int off = sBase[code] + rank;
-                for (int w = 0; w < wave; ++w) off += sCnt[w * NC + code];
-                idx[off] = k;
-            }
-            __syncthreads();
-            if ((int)threadIdx.x < NC) {
-                int add = 0;
-                for (int w = 0; w < nw; ++w) add += sCnt[w * NC + threadIdx.x];
-                sBase[threadIdx.x] += add;
-            }
-            __syncthreads();
-        }
-    }
+    // species_mask: the species pushed in this step; the outboxes of the
+    // others hold nothing of this step
+    const int s = ts % p.nspecies;
+    const int n = ((p.species_mask >> s) & 1u) ? (int)min((int64_t)p.ob_cnt[ts], p.ob_cap) : 0;
+    bucket_outbox<R, D>(p, ts, n, sScratch, sScratch + MAX_WAVES * ncodes<D>());
 }
 
 // Receive incoming particles: append, per direction code in increasing
@@ -1028,7 +1048,10 @@ __global__ void __launch_bounds__(1024) k_migrate_in(Params<R> p)
                 const int32_t *boff = p.ob_boff + (int64_t)sts * (NC + 1);
                 sSrc[code] = sts;
                 sB0[code] = boff[code];
-                n_in = code == centre_code<D>() ? 0 : boff[code + 1] - boff[code];
+                // species not pushed in this step have no leavers (their
+                // bucket starts may be an earlier step's)
+                const bool pushed = (p.species_mask >> s) & 1u;
+                n_in = code == centre_code<D>() || !pushed ? 0 : boff[code + 1] - boff[code];
             }
             int x = n_in;
 #pragma unroll
