@@ -37,16 +37,16 @@ METRIC = "particle-steps/sec (push+deposit+FDTD) FP32 vs FP64 at 1 GPU; % HBM ro
 # contents without comments), precision, tile edge, cells per side and
 # particles per cell: any other kernel code reports no traffic.
 MEASURED_PUSH_TRAFFIC = {
-    ("0681571432fda81a", "fp32", 16, 1024, 16): 1668288476,
-    ("0681571432fda81a", "fp64", 16, 1024, 16): 3196000366,
+    ("2bb5b5e4165595fb", "fp32", 16, 1024, 16): 1674617957,
+    ("2bb5b5e4165595fb", "fp64", 16, 1024, 16): 3202604049,
 }
 
 # wave64 VALU instructions per 64 particles of the same push, from rocprofv3
-# --pmc SQ_INSTS_VALU over the first 40 launches of a run (same key), and the
+# --pmc SQ_INSTS_VALU over launches 5-39 of a run (same key), and the
 # chip's VALU issue peak: 256 CUs x 4 SIMDs, one wave64 instruction per 4
 # clocks per SIMD (16 lanes; FP32 not packed) at 2.4 GHz
 MEASURED_PUSH_VALU_PER_64 = {
-    ("0681571432fda81a", "fp32", 16, 1024, 16): 392.0,
+    ("2bb5b5e4165595fb", "fp32", 16, 1024, 16): 399.2,
 }
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
