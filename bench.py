@@ -193,9 +193,22 @@ def run_gpu(plasma, args, precision, steps, warmup, tile, block=256, profile_onl
         code = sim.error()
         sim.close()
         return code
+
+    def spin_us():
+        # a kernel that waits 20,000 shader-clock cycles: its duration
+        # follows the core clock (outside every timed region)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        torch.cuda._sleep(20000)
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) * 1e3
+
+    torch.cuda._sleep(1000)          # load the spin kernel once, before the warm-up
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
+    clock = {"spin_20k_cycles_us_before_timed_steps": spin_us()}
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     t0 = time.perf_counter()
     for k in range(steps):
@@ -203,6 +216,7 @@ def run_gpu(plasma, args, precision, steps, warmup, tile, block=256, profile_onl
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     push_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    clock["spin_20k_cycles_us_after_timed_steps"] = spin_us()
     # context beside the timed window (not the headline): the same run
     # continued to step 40, then steps 40-60 timed with events, past the
     # slower core clock of the first ~30 ms after the GPU leaves idle
@@ -219,6 +233,7 @@ def run_gpu(plasma, args, precision, steps, warmup, tile, block=256, profile_onl
         torch.cuda.synchronize()
         later = {"steps": "40-60", "push_ms": float(np.mean([a.elapsed_time(b) for a, b, _ in ev2])),
                  "ms_per_step_events": float(np.mean([a.elapsed_time(c) for a, _, c in ev2]))}
+        clock["spin_20k_cycles_us_after_step_60"] = spin_us()
     sim.diagnostics()
     # one more (untimed) step so that the diagnostics also state the
     # discrete continuity residual of a step
@@ -228,7 +243,7 @@ def run_gpu(plasma, args, precision, steps, warmup, tile, block=256, profile_onl
     sim.close()
     del sim
     torch.cuda.empty_cache()
-    return dict(seconds=dt, push_ms=push_ms, diag=diag, later=later)
+    return dict(seconds=dt, push_ms=push_ms, diag=diag, later=later, clock=clock)
 
 
 def valu_roofline(key_hash, prec, tile, args, n_p, push_ms):
@@ -898,6 +913,7 @@ def main():
         "step_roofline_frac": algorithmic_bytes(D, 4, n_p, n_c) * value / n_p / 1e9 / HBM_PEAK_GBS,
         "valu_roofline": valu_roofline(kernel_source_hash(), "fp32", tile32, args, n_p, r32["push_ms"]),
         "same_run_steps_40_60": r32["later"],
+        "clock_probe": r32["clock"],
         "diagnostics_fp32": {k: r32["diag"][k] for k in ("gauss_max", "continuity_max", "divb_max", "field_energy",
                                                          "kinetic_energy", "particles", "near_face",
                                                          "max_segment_fill", "status")},
