@@ -47,6 +47,7 @@ MEASURED_PUSH_TRAFFIC = {
 # clocks per SIMD (16 lanes; FP32 not packed) at 2.4 GHz
 MEASURED_PUSH_VALU_PER_64 = {
     ("2bb5b5e4165595fb", "fp32", 16, 1024, 16): 399.2,
+    ("2bb5b5e4165595fb", "fp64", 16, 1024, 16): 438.3,
 }
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
@@ -935,6 +936,7 @@ def main():
                        "gauss_max": r64["diag"]["gauss_max"], "continuity_max": r64["diag"]["continuity_max"],
                        "status": r64["diag"]["status"],
                        "vs_oracle_1step_rel_l2": err64,
+                       "valu_roofline": valu_roofline(kernel_source_hash(), "fp64", tile64, args, n_p, r64["push_ms"]),
                        "same_run_steps_40_60": r64["later"],
                        "vs_oracle_common_state_rel_l2": cs64}
     print(json.dumps(out), flush=True)
