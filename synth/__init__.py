@@ -248,9 +248,24 @@ def turbulence(n: int = 1024, ppc: int = 16, theta: float = 0.3, sigma: float = 
     return _pair(2, dims, c, qabs, x, ue, x.copy(), up, E, B, meta)
 
 
+def _chunks(total: int, size: int):
+    return [(a, min(a + size, total)) for a in range(0, total, size)]
+
+
+def _run_seeded(seed: int, tasks, fn, workers: int):
+    """fn(rng, task) for every task, each with its own generator spawned from
+    seed in task order, on a pool of threads (numpy's generators and array
+    arithmetic release the interpreter lock).  The results depend on seed and
+    on the task list only, not on the order the threads run them."""
+    from concurrent.futures import ThreadPoolExecutor
+    kids = np.random.SeedSequence(seed).spawn(len(tasks))
+    with ThreadPoolExecutor(max_workers=max(1, workers)) as ex:
+        list(ex.map(lambda a: fn(np.random.default_rng(a[0]), a[1]), zip(kids, tasks)))
+
+
 def shock(n: tuple = (1024, 128, 128), x_shock: int = 256, ppc_down: int = 32, ppc_up: int = 8,
           theta_down: float = 3.286, gamma_up: float = 10.0, theta_up: float = 1e-4, Rp: float = 10.0,
-          c: float = 0.45, seed: int = BASE_SEED + 3, log=None) -> Plasma:
+          c: float = 0.45, seed: int = BASE_SEED + 3, log=None, workers: int | None = None) -> Plasma:
     """3D3V pre-shocked pair plasma between conducting walls in x (Sect. 5.2
     setup, started from a shocked state): for x < x_shock a hot plasma at
     rest (Maxwell-Juttner theta_down, ppc_down per species, mean Lorentz
@@ -258,23 +273,55 @@ def shock(n: tuple = (1024, 128, 128), x_shock: int = 256, ppc_down: int = 32, p
     upstream beam moving towards the wall at x = 0 (Lorentz factor
     gamma_up, theta_up boosted, ppc_up per species).  |q| follows the
     upstream (ppc_up, <gamma> = gamma_up); E = B = 0.  Each positron sits
-    on an electron (zero charge density at the start)."""
-    rng = np.random.default_rng(seed)
+    on an electron (zero charge density at the start).
+
+    Positions come layer by layer (one particle in every cell per layer,
+    the downstream layers first), as quiet_positions lays them out; the
+    layers and the four-velocities are drawn in fixed chunks, each from its
+    own generator spawned from seed, on `workers` threads (default: up to
+    16), so the state depends on the seed alone."""
+    import os
+    workers = workers or min(16, os.cpu_count() or 1)
     nx, ny, nz = n
-    down = quiet_positions(rng, 3, (x_shock, ny, nz), ppc_down)
-    up = quiet_positions(rng, 3, (nx - x_shock, ny, nz), ppc_up)
-    up[0] += x_shock
-    x = np.concatenate([down, up], axis=1)
-    del down, up
+    regions = [((x_shock, ny, nz), ppc_down, 0), ((nx - x_shock, ny, nz), ppc_up, x_shock)]
+    total = sum(ppc * r[0] * r[1] * r[2] for r, ppc, _ in regions)
+    x = np.empty((3, total))
+    layers, o = [], 0
+    for dims, ppc, x0 in regions:
+        N = dims[0] * dims[1] * dims[2]
+        cells = np.arange(N, dtype=np.int64)
+        idx = [(cells % dims[0]).astype(np.float64), ((cells // dims[0]) % dims[1]).astype(np.float64),
+               (cells // (dims[0] * dims[1])).astype(np.float64)]
+        for _ in range(ppc):
+            layers.append((o, N, dims, idx, x0))
+            o += N
+
+    def fill_layer(rng, t):
+        o, N, dims, idx, x0 = t
+        for d in range(3):
+            v = idx[d] + rng.random(N)
+            v = np.where(v >= dims[d], 0.0, v)
+            x[d, o:o + N] = v + x0 if d == 0 else v
+
+    _run_seeded(seed, layers, fill_layer, workers)
     if log:
-        log(f"shock: {x.shape[1]} positions per species")
+        log(f"shock: {total} positions per species")
     nd = ppc_down * x_shock * ny * nz
-    nu = x.shape[1] - nd
+    step = 1 << 22
     us = []
     for k in range(2):
-        u = np.empty((3, nd + nu))
-        u[:, :nd] = sample_mj(rng, theta_down, nd)
-        u[:, nd:] = boost_x(rng, sample_mj(rng, theta_up, nu), gamma_up, -1.0)
+        u = np.empty((3, total))
+        tasks = [(a, b, True) for a, b in _chunks(nd, step)] + \
+                [(nd + a, nd + b, False) for a, b in _chunks(total - nd, step)]
+
+        def fill_u(rng, t):
+            a, b, down = t
+            if down:
+                u[:, a:b] = sample_mj(rng, theta_down, b - a)
+            else:
+                u[:, a:b] = boost_x(rng, sample_mj(rng, theta_up, b - a), gamma_up, -1.0)
+
+        _run_seeded(seed * 4 + 1 + k, tasks, fill_u, workers)
         us.append(u)
         if log:
             log(f"shock: four-velocities of species {k}")
