@@ -3,7 +3,8 @@
 8^3 tiles, the per-tile push with 512-thread work-groups, conducting walls
 in x, segment capacities twice the dilated initial counts; every step is
 the fused sequence (push with push_half_b1 in LDS, the two half B updates,
-fold with the E update, migration).
+fold with the E update, migration).  Both push launches the benchmark
+times are checked: one work-group per segment, and the persistent walker.
 
 After 3 steps from the generated state (E and B no longer zero) one more
 step is checked against the oracle on sampled tiles, from the GPU's own
@@ -75,7 +76,8 @@ def slots_and_tiles(off, cnt, s, tile_set):
     return sl[o], tid[o]
 
 
-def test_shock_full_size_sampled_tiles():
+@pytest.mark.parametrize("walker", ["per_tile", "persistent"])
+def test_shock_full_size_sampled_tiles(walker):
     from paper_1906_06306_amd import _lib as L
     from paper_1906_06306_amd.sim import PicSim
     n, T, D = N3, T3, 3
@@ -84,9 +86,10 @@ def test_shock_full_size_sampled_tiles():
     c = plasma.c
     q = [sp.q for sp in plasma.species]
     sgn = [sp.s for sp in plasma.species]
-    print(f"[gpu] shock {n}, {plasma.nparticles} particles, FP32, T=8^3, block 512, walls", flush=True)
+    print(f"[gpu] shock {n}, {plasma.nparticles} particles, FP32, T=8^3, block 512, walls, {walker}", flush=True)
+    opts = L.PIC_OPT_TRACK | (L.PIC_OPT_PERSISTENT if walker == "persistent" else 0)
     sim = PicSim(plasma, tile=T, precision="fp32", tile_capacity="auto", capacity_factor=2.0,
-                 options=L.PIC_OPT_TRACK, walls=True, block=512)
+                 options=opts, walls=True, block=512)
     del plasma
     sim.step(3, fused=True, half_b_in_push=True)
     assert sim.error() == 0
