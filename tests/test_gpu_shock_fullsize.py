@@ -24,6 +24,10 @@ in y and z.  Cell decisions taken differently in FP32 and FP64 (an end point
 within rounding of a cell face) are handled as in the 2D full-size test:
 the oracle deposits such a particle from the kernel's end point, and every
 one of them must be flagged near a face.  Relative L2 1e-5.
+
+A second test takes the first step from the FP64 input itself (the
+FP32/FP64 cell rule at full size in 3D): cells may differ from the
+oracle's FP64 step only at particles flagged near a face.
 """
 import numpy as np
 import pytest
@@ -166,6 +170,68 @@ def test_shock_full_size_sampled_tiles(walker):
     assert unflagged == 0
     assert np.abs(J[:, cells]).max() > 0
     assert rj < TOL and re < TOL and rb < TOL
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+
+
+def test_shock_full_size_fp32_cells_vs_fp64_input():
+    """The FP32/FP64 cell rule at full size in 3D: one FP32 step from the
+    FP64 input (positions rounded to FP32 tile-local coordinates at init)
+    against the oracle's FP64 step from the same input, for every particle
+    that ends in the 27 tiles around the sampled centres (matched through
+    origin ids to its input index).  Cells may differ only at particles
+    flagged near a face after the FP32 step; an unflagged mismatch fails."""
+    from paper_1906_06306_amd import _lib as L
+    from paper_1906_06306_amd.sim import PicSim
+    n, T, D = N3, T3, 3
+    nt = tiles.tile_grid(n, T, D)
+    plasma = synth.shock()
+    c = plasma.c
+    print(f"[gpu] shock {n} from the FP64 input, {plasma.nparticles} particles, FP32", flush=True)
+    sim = PicSim(plasma, tile=T, precision="fp32", tile_capacity="auto", capacity_factor=2.0,
+                 options=L.PIC_OPT_TRACK, walls=True, block=512)
+    cap = int(sim.layout.capacity_total)
+    ids_dev = sim._view(sim.layout.off_ids, cap, torch.int32)
+    ids0 = ids_dev.clone()                 # after init: index in the concatenated input
+    sim.step(1, fused=True, half_b_in_push=True)
+    assert sim.error() == 0
+    total, flagged = sim.sort_migrate(flagged_capacity=1 << 22)
+    assert total <= 1 << 22
+    flagged = np.sort(flagged)
+    pos, u, _, off, cnt = sim.particle_views()
+    offh, cnth = off.cpu().numpy(), cnt.cpu().numpy()
+    inner = set().union(*[around(nt, ct, 1) for ct in CENTRES])
+    # the oracle's first step from the input: push_half_b1, interp, push
+    Bh = np.ascontiguousarray(plasma.B, dtype=np.float64).copy()
+    E0 = np.ascontiguousarray(plasma.E, dtype=np.float64)
+    oracle.advance_b(D, n, 0.5 * c, E0, Bh)
+    base = checked = mismatched = unflagged = 0
+    for s, sp in enumerate(plasma.species):
+        sl, tid = slots_and_tiles(offh, cnth, s, inner)
+        it = torch.as_tensor(sl, device=sim.device)
+        k = ids0[ids_dev[it].long()].cpu().numpy().astype(np.int64) - base
+        base += sp.x.shape[1]
+        assert (k >= 0).all() and (k < sp.x.shape[1]).all() and np.unique(k).size == k.size
+        x1 = np.ascontiguousarray(sp.x[:, k])
+        uo = np.ascontiguousarray(sp.u[:, k])
+        Ep, Bp = oracle.interp(D, n, E0, Bh, x1)
+        oracle.boris(c, sp.s, Ep, Bp, uo)
+        x2 = x1.copy()
+        oracle.move(D, c, uo, x2)
+        xg = tiles.to_global(tid, pos[:, it].cpu().numpy(), n, T, D)
+        for d in (1, 2):                                     # unwrap across the periodic seams
+            xg[d] += n[d] * np.round((x2[d] - xg[d]) / n[d])
+        assert np.abs(xg - x2).max() < 4e-6
+        assert rel(u[:, it].cpu().numpy().astype(np.float64), uo) < TOL
+        bad = (np.floor(xg) != np.floor(x2)).any(axis=0)
+        checked += k.size
+        mismatched += int(bad.sum())
+        unflagged += int((~np.isin(sl[bad], flagged)).sum())
+    print(f"[gpu] shock full size from the FP64 input: {checked} particles, {mismatched} cell mismatches, "
+          f"{total} flagged, {unflagged} unflagged", flush=True)
+    assert checked > 1_000_000
+    assert unflagged == 0
     sim.close()
     del sim
     torch.cuda.empty_cache()
