@@ -196,11 +196,17 @@ def _pair(D, n, c, qabs, xe, ue, xp, up, E, B, meta):
 
 
 def weibel(nx: int = 512, ppc: int = 64, gamma_b: float = 3.0, theta: float = 0.01,
-           Rp: float = 10.0, c: float = 0.45, seed: int = BASE_SEED + 1) -> Plasma:
+           Rp: float = 10.0, c: float = 0.45, seed: int = BASE_SEED + 1, beam_axis: int = 0) -> Plasma:
     """1D3V pair plasma, two counter-streaming beams along x with Lorentz
     factor gamma_b and Maxwell-Juttner spread theta in the beam frame.
     Each species is split half/half between the +x and -x beams; each
-    positron sits on an electron (zero initial charge density)."""
+    positron sits on an electron (zero initial charge density).
+
+    beam_axis = 1 streams the beams along y instead, across the grid
+    direction (the filamentation geometry of Sect. 5.1, where the
+    perturbation's wave vector is normal to the beams): the same draws with
+    the x and y momentum components exchanged, which leaves the isotropic
+    rest-frame spread unchanged."""
     rng = np.random.default_rng(seed)
     n = (nx, 1, 1)
     x = quiet_positions(rng, 1, n, ppc)
@@ -215,12 +221,17 @@ def weibel(nx: int = 512, ppc: int = 64, gamma_b: float = 3.0, theta: float = 0.
         u[:, half:] = boost_x(rng, u0[:, half:], gamma_b, -1.0)
         us.append(u)
     del sign
+    if beam_axis not in (0, 1):
+        raise ValueError("beam_axis is 0 (beams along x) or 1 (along y)")
+    if beam_axis == 1:
+        us = [np.ascontiguousarray(u[[1, 0, 2]]) for u in us]
     mg = gamma_b * mean_gamma_mj(theta)
     qabs = charge_from_skin_depth(c, Rp, ppc, mg)
     N = nx
     E = np.zeros((3, N))
     B = np.zeros((3, N))
-    meta = dict(workload="weibel", ppc=ppc, theta=theta, gamma_b=gamma_b, Rp=Rp, mean_gamma=mg)
+    meta = dict(workload="weibel", ppc=ppc, theta=theta, gamma_b=gamma_b, Rp=Rp, mean_gamma=mg,
+                beam_axis=beam_axis)
     return _pair(1, n, c, qabs, x, us[0], x.copy(), us[1], E, B, meta)
 
 
