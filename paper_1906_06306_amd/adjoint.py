@@ -64,16 +64,19 @@ def backward(sim: PicSim, ckpts: dict, nsteps: int, lE, lB, lpos=None, lu=None, 
         w1 = min(w0 + window, nsteps)
         sim.restore(ckpts[w0])
         states = [ckpts[w0]]
-        for _ in range(w0, w1):
+        for j in range(w0, w1):
             L.check(fn(sim.ctx, STEP_FLAGS))
-            states.append(sim.snapshot())
+            if j + 1 < w1:                 # the last state stays in the workspace
+                states.append(sim.snapshot())
+        # Neither the unpermute nor the adjoint step writes the state
+        # regions, so the state a reversed step leaves in the workspace (the
+        # one before it) is the one the next reversed step starts from.
         for k in range(w1 - 1, w0 - 1, -1):
-            sim.restore(states[k + 1 - w0])
             lb.zero_()
             ub.zero_()
-            sim.unpermute(la, ua, lb, ub, cap)
+            sim.unpermute(la, ua, lb, ub, cap)      # from the state after step k
             sim.restore(states[k - w0])
-            sim.adjoint_step(lb, ub, lE, lB)
+            sim.adjoint_step(lb, ub, lE, lB)        # from the state before it
             la, lb = lb, la
             ua, ub = ub, ua
         del states
