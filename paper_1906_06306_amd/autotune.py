@@ -49,8 +49,12 @@ def tune(plasma, precision: str = "fp32", blocks=(256,), capacity_factor: float 
          log=None):
     """Return (best (T, block), {(T, block): seconds per step})."""
     elem = 8 if precision == "fp64" else 4
+    edges = candidates(plasma, elem)
+    if not edges:
+        raise ValueError(f"no tile edge of 8, 16 or 32 divides every side of {tuple(plasma.n[:plasma.D])} "
+                         "and fits the LDS; give the tile explicitly")
     results = {}
-    for T in candidates(plasma, elem):
+    for T in edges:
         for blk in blocks:
             sim = PicSim(plasma, tile=(T,) * plasma.D, precision=precision, block=blk,
                          capacity_factor=capacity_factor)
