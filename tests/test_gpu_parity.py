@@ -61,12 +61,21 @@ def test_init_binning_bit_exact(D, n, T, ppc, prec):
     plasma = synth.small_random(D, n, ppc, seed=3 + D)
     sim = make_sim(plasma, T, prec)
     dt = np.float64 if prec == "fp64" else np.float32
+    counts = sim.counts_host()
+    boxes = sim.state_boxes()
+    ntiles = int(np.prod(tiles.tile_grid(n, T, D)))
     for s, sp in enumerate(plasma.species):
         tid, xl, order = tiles.bin_global(sp.x, n, T, D, dt)
         g_tid, g_xl, g_u = sim.particles_host(0, s)
         assert np.array_equal(g_tid, tid[order])
         assert np.array_equal(g_xl, xl[:, order])
         assert np.array_equal(g_u, sp.u[:, order].astype(dt))
+        # per-tile counts, and the FP64 state read back: binning it again
+        # gives the same tiles and local coordinates (an exact round trip)
+        assert np.array_equal(counts[:ntiles, s], np.bincount(tid, minlength=ntiles))
+        r_tid, r_xl, r_order = tiles.bin_global(boxes[0].pos[s], n, T, D, dt)
+        assert np.array_equal(r_order, np.arange(r_tid.size))
+        assert np.array_equal(r_tid, g_tid) and np.array_equal(r_xl, g_xl)
     E, B, J = sim.fields_host(0)
     assert np.array_equal(E, plasma.E.astype(dt).astype(np.float64))
     assert not J.any()
