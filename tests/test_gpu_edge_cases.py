@@ -8,7 +8,10 @@ ids):
 * particles started exactly on cell faces and tile faces;
 * particles at rest in zero fields, half of them on faces: the current is
   exactly zero, nothing moves, and every particle on a face stays flagged
-  as near a face.
+  as near a face;
+* a NaN four-velocity, and a move of a whole cell at a Courant number of 1:
+  the device error is latched and reported, the particle stays, and the
+  rest of the step is the oracle's step of the other particles.
 """
 import math
 
@@ -187,4 +190,80 @@ def test_particles_at_rest_in_zero_fields(prec):
         assert a == b
         assert not u1.any()
     assert sim.diagnostics()["near_face"] == on_face
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_nonfinite_momentum_is_reported_and_contained(prec):
+    """A particle whose four-velocity is NaN latches PIC_E_NONFINITE (read
+    back, and cleared, by pic_error; latched again by the next step and
+    then reported in the diagnostics' status), stays where it was and
+    deposits nothing: the fields are the oracle's step of the other
+    particles."""
+    from paper_1906_06306_amd import _lib as L
+    from paper_1906_06306_amd.sim import PicSim
+    full = synth.small_random(2, (32, 24), 4, seed=48, field_amp=0.05)
+    xs = [sp.x.copy() for sp in full.species]
+    us = [sp.u.copy() for sp in full.species]
+    us[0][:, 7] = np.nan
+    p = plasma_of(2, (32, 24), xs, us, 0.05, seed=49)
+    print(f"[gpu] NaN momentum, {p.nparticles} particles, {prec}", flush=True)
+    sim = PicSim(p, tile=(8, 8), precision=prec, capacity_factor=3.0)
+    sim.step(1, fused=True, half_b_in_push=True)
+    err = sim.error()
+    assert err & L.PIC_E_NONFINITE, err
+    assert sim.error() == 0                         # read and cleared
+    # the oracle's step without that particle
+    q = plasma_of(2, (32, 24), [np.delete(xs[0], 7, axis=1), xs[1]], [np.delete(us[0], 7, axis=1), us[1]],
+                  0.05, seed=49)
+    st = oracle.State(q)
+    st.step(1)
+    E, B, J = sim.fields_host(0)
+    tol = TOL[prec]
+    assert rel(J, st.J) < tol and rel(E, st.E) < tol and rel(B, st.B) < tol
+    tid, xl, u = sim.particles_host(0, 0)
+    bad = ~np.isfinite(u).all(axis=0)
+    assert bad.sum() == 1
+    x_bad = tiles.to_global(tid[bad], xl[:, bad], (32, 24, 1), sim.T, 2)
+    assert np.abs(x_bad[:, 0] - xs[0][:, 7]).max() < (1e-12 if prec == "fp64" else 4e-6)
+    assert np.isfinite(sim.particles_host(0, 1)[2]).all()
+    sim.step(1, fused=True, half_b_in_push=True)
+    assert sim.diagnostics()["status"] & L.PIC_E_NONFINITE
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64"])
+def test_cfl_violation_is_reported(prec):
+    """At a Courant number of 1 (1D) a particle with u = 1e10 moves
+    c u / gamma, a whole cell after rounding: PIC_E_CFL is latched and the
+    particle is not moved; the slow particles step as in the oracle.  FP64
+    only: there 1 + u^2 = 1e20 and its correctly rounded reciprocal square
+    root give u / gamma = 1 exactly, while the FP32 push's reciprocal square
+    root (about 1 ulp) may land either side of 1."""
+    from paper_1906_06306_amd import _lib as L
+    from paper_1906_06306_amd.sim import PicSim
+    rng = np.random.default_rng(50)
+    npart = 200
+    xs = [rng.uniform(0.0, 64.0, (1, npart)) for _ in range(2)]
+    us = [0.05 * rng.standard_normal((3, npart)) for _ in range(2)]
+    us[1][:, 3] = (1e10, 0.0, 0.0)
+    p = plasma_of(1, (64,), xs, us, 0.0, seed=51, c=1.0)
+    print(f"[gpu] CFL violation, {p.nparticles} particles, c = 1, {prec}", flush=True)
+    sim = PicSim(p, tile=(16,), precision=prec, capacity_factor=3.0)
+    sim.step(1, fused=True, half_b_in_push=True)
+    err = sim.error()
+    assert err & L.PIC_E_CFL, err
+    assert not err & L.PIC_E_NONFINITE
+    tid, xl, u = sim.particles_host(0, 1)
+    fast = u[0] > 1e9
+    assert fast.sum() == 1
+    xg = tiles.to_global(tid[fast], xl[:, fast], (64, 1, 1), sim.T, 1)
+    assert abs(xg[0, 0] - xs[1][0, 3]) < (1e-12 if prec == "fp64" else 4e-6)
+    q = plasma_of(1, (64,), [xs[0], np.delete(xs[1], 3, axis=1)], [us[0], np.delete(us[1], 3, axis=1)], 0.0,
+                  seed=51, c=1.0)
+    st = oracle.State(q)
+    st.step(1)
+    E, B, J = sim.fields_host(0)
+    tol = TOL[prec]
+    assert rel(J, st.J) < tol and rel(E, st.E) < tol
     sim.close()
