@@ -407,6 +407,38 @@ def test_capacity_overflow_is_reported():
     assert e.value.code & L.PIC_E_CAPACITY
 
 
+def test_outbox_overflow_is_reported():
+    """More leavers in a step than a segment's outbox holds latch
+    PIC_E_CAPACITY (forced from the host with the smallest outbox, 64 slots,
+    against ~100 leavers per 8x8 tile of a hot plasma at 32 particles per
+    cell; the push checks every outbox slot)."""
+    from paper_1906_06306_amd import _lib as L
+    plasma = synth.small_random(2, (32, 32), 32, theta=1.0, seed=5)
+    sim = make_sim(plasma, (8, 8), "fp32", outbox_capacity=1, capacity_factor=2.0)
+    assert sim.layout.outbox_capacity == 64
+    sim.step(1, fused=True, half_b_in_push=True)
+    assert sim.error() & L.PIC_E_CAPACITY
+    sim.close()
+
+
+def test_arrivals_beyond_capacity_are_reported():
+    """A segment that receives more particles than its free slots latches
+    PIC_E_CAPACITY in the migration (forced from the host: every segment
+    holds exactly its capacity, the left half of the box streams into the
+    right half at rest; the migration checks every destination slot)."""
+    from paper_1906_06306_amd import _lib as L
+    plasma = synth.small_random(2, (32, 32), 16, field_amp=0.0, seed=6)
+    for sp in plasma.species:
+        sp.u[:] = 0.0
+        sp.u[0, sp.x[0] < 16.0] = 3.0
+    cap = np.full((16, 2), 1024, dtype=np.int64)          # 16 per cell x 64 cells, a multiple of 64
+    sim = make_sim(plasma, (8, 8), "fp32", tile_capacity=cap, block=64)
+    assert sim.error() == 0
+    sim.step(1, fused=True, half_b_in_push=True)
+    assert sim.error() & L.PIC_E_CAPACITY
+    sim.close()
+
+
 def test_positions_outside_box_are_reported():
     from paper_1906_06306_amd import _lib as L
     plasma = synth.small_random(2, (32, 32), 2, seed=2)
