@@ -319,10 +319,18 @@ class PicSim:
                 o += c
         return out
 
+    def ids_view(self) -> torch.Tensor:
+        """The origin ids (int32 per particle slot, `PIC_OPT_TRACK`) as a
+        device view of the workspace: after init the index in the
+        concatenated input, after a step the slot the particle held before
+        it."""
+        if not self.cfg.options & L.PIC_OPT_TRACK:
+            raise ValueError("origin ids need options=PIC_OPT_TRACK")
+        return self._view(self.layout.off_ids, int(self.layout.capacity_total), torch.int32)
+
     def ids_host(self):
         torch.cuda.synchronize(self.device)
-        cap = int(self.layout.capacity_total)
-        return self._view(self.layout.off_ids, cap, torch.int32).cpu().numpy()
+        return self.ids_view().cpu().numpy()
 
     def error(self) -> int:
         code = L.lib().pic_error(self.ctx)

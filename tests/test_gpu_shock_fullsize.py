@@ -100,8 +100,7 @@ def test_shock_full_size_sampled_tiles(walker):
     E0, B0, _ = sim.fields_host(0)
     assert np.abs(E0).max() > 0 and np.abs(B0).max() > 0
     pos, u, _, off, cnt = sim.particle_views()
-    cap = int(sim.layout.capacity_total)
-    ids_dev = sim._view(sim.layout.off_ids, cap, torch.int32)
+    ids_dev = sim.ids_view()
     inner = set().union(*[around(nt, ct, 1) for ct in CENTRES])
     outer = set().union(*[around(nt, ct, 2) for ct in CENTRES])
     offh, cnth = off.cpu().numpy(), cnt.cpu().numpy()
@@ -191,8 +190,7 @@ def test_shock_full_size_fp32_cells_vs_fp64_input():
     print(f"[gpu] shock {n} from the FP64 input, {plasma.nparticles} particles, FP32", flush=True)
     sim = PicSim(plasma, tile=T, precision="fp32", tile_capacity="auto", capacity_factor=2.0,
                  options=L.PIC_OPT_TRACK, walls=True, block=512)
-    cap = int(sim.layout.capacity_total)
-    ids_dev = sim._view(sim.layout.off_ids, cap, torch.int32)
+    ids_dev = sim.ids_view()
     ids0 = ids_dev.clone()                 # after init: index in the concatenated input
     sim.step(1, fused=True, half_b_in_push=True)
     assert sim.error() == 0
