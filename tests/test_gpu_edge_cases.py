@@ -13,7 +13,6 @@ ids):
   the device error is latched and reported, the particle stays, and the
   rest of the step is the oracle's step of the other particles.
 """
-import math
 
 import numpy as np
 import pytest
