@@ -37,8 +37,8 @@ METRIC = "particle-steps/sec (push+deposit+FDTD) FP32 vs FP64 at 1 GPU; % HBM ro
 # contents without comments), precision, tile edge, cells per side and
 # particles per cell: any other kernel code reports no traffic.
 MEASURED_PUSH_TRAFFIC = {
-    ("2bb5b5e4165595fb", "fp32", 16, 1024, 16): 1674617957,
-    ("2bb5b5e4165595fb", "fp64", 16, 1024, 16): 3202604049,
+    ("7ea8fa693dd327a3", "fp32", 16, 1024, 16): 1676796437,
+    ("7ea8fa693dd327a3", "fp64", 16, 1024, 16): 3200055419,
 }
 
 # wave64 VALU instructions per 64 particles of the same push, from rocprofv3
@@ -46,8 +46,8 @@ MEASURED_PUSH_TRAFFIC = {
 # chip's VALU issue peak: 256 CUs x 4 SIMDs, one wave64 instruction per 4
 # clocks per SIMD (16 lanes; FP32 not packed) at 2.4 GHz
 MEASURED_PUSH_VALU_PER_64 = {
-    ("2bb5b5e4165595fb", "fp32", 16, 1024, 16): 399.2,
-    ("2bb5b5e4165595fb", "fp64", 16, 1024, 16): 438.3,
+    ("7ea8fa693dd327a3", "fp32", 16, 1024, 16): 387.4,
+    ("7ea8fa693dd327a3", "fp64", 16, 1024, 16): 425.3,
 }
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
